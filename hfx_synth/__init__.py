@@ -344,9 +344,12 @@ def build_blocks(cell: Cell, seed: int, p: Params):
 SEED0 = 2009_12505
 
 
-def make_cell(kind: str, n=(1, 1, 1), species_table=((13, 40),), species=None, a: float = A_SI) -> Cell:
+def make_cell(kind: str, n=(1, 1, 1), species_table=((13, 40),), species=None, a: float = A_SI,
+              lattice=None, pos=None) -> Cell:
     if kind == "primitive":
         lat, pos = diamond_primitive(a)
+    elif kind == "custom":
+        lat, pos = np.asarray(lattice, np.float64), np.asarray(pos, np.float64)
     else:
         lat, pos = diamond_conventional(*n, a=a)
     sp = np.zeros(pos.shape[0], np.int32) if species is None else np.asarray(species, np.int32)
@@ -397,7 +400,7 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
                 setattr(p, f, kw.pop(f))
         cells = [make_cell(kw.pop("kind", "primitive"), kw.pop("n", (1, 1, 1)),
                            species_table=kw.pop("species_table", ((3, 5),)), species=kw.pop("species", None),
-                           a=kw.pop("a", A_SI))]
+                           a=kw.pop("a", A_SI), lattice=kw.pop("lattice", None), pos=kw.pop("pos", None))]
         th = 0.0 if eps is None else eps
     if kw:
         raise TypeError(f"unknown keywords {sorted(kw)}")
