@@ -303,6 +303,10 @@ def _build(kind, cell, row, col, R, d, seed, p, spd):
     for u in uniq:
         a, b = int(u[0]), int(u[1])
         qd = u[2:5]
+        flip = False
+        if kind in ("V", "D") and (b, *(-qd).tolist()) < (a, *qd.tolist()):
+            # V(R) = V(-R)^T and D(R) = D(-R)^T exactly: draw the canonical orientation, transpose
+            a, b, qd, flip = b, a, -qd, True
         dv = qd.astype(np.float64) * _QUANT
         A, B = spd[a], spd[b]
         if kind == "C":
@@ -320,6 +324,8 @@ def _build(kind, cell, row, col, R, d, seed, p, spd):
         else:
             rd = np.linalg.norm(dv[None, None, :] + B.t[None, :, :] - A.t[:, None, :], axis=2)
             blk = kernel_d(rd, p) * (A.u @ B.u.T)
+        if flip:
+            blk = blk.T
         datas.append(np.ascontiguousarray(blk, np.float64).reshape(-1))
         sizes.append(blk.size)
     sizes = np.asarray(sizes, np.int64)

@@ -1,0 +1,206 @@
+/*
+ * hfx.h - C ABI of the MI355X (gfx950) library that builds the screened,
+ * linear-scaling periodic Hartree-Fock exchange matrix under the localized
+ * resolution of identity (Lin, Ren & He, "Efficient Hybrid Density Functional
+ * Calculations for Large Periodic Systems Using Numerical Atomic Orbitals").
+ *
+ * What is computed (Sec. II, eqs. HFX_ERIs, LRI, HFX_LRI, HFX_split,
+ * partial_integrals; Sec. III A, Algorithms 2 and 3; Sec. III B-C,
+ * Algorithms 4 and 5):
+ *
+ *   Sigma^X_{Ii,Jj}(R) = - sum_{K,L} sum_{k,l} (Ii Kk | Jj Ll) D_{Kk,Ll}
+ *   (Ii Kk | Jj Ll)    = sum_{A in {I,K}} sum_{B in {J,L}} C^{A} V_{AB} C^{B}
+ *
+ * evaluated as the <A,B> loop of Algorithm 2 in the order C((VC)D) of
+ * Algorithm 3, with the block pre-screening of C, V, D by max-abs (Sec. III B),
+ * the CS-ERI quartet test (Sec. III C 2, eq. CS-ERI) and the three-stage
+ * Cauchy-Schwarz matrix screening (eq. CS_upper_bounds, Algorithm 4), and
+ *   E_x = 1/2 <D, Sigma^X>       (Algorithm 5, "Calculate E^X").
+ *
+ * Conventions (readings of points the paper leaves open):
+ *  - All indices are 0-based, lengths in elements, lengths in bohr, energies in Hartree.
+ *  - An atom reference is (home-cell atom index, integer lattice vector R) (eq. AO).
+ *  - Block-sparse periodic tensors hold one dense row-major FP64 block per
+ *    (row atom, column atom, R); the row atom is in the home cell, the column
+ *    atom in cell R.  Shapes:  C: [n_abf(row)][n_ao(row)][n_ao(col)]  (the ABF
+ *    sits on the row atom, which also carries the first AO index, eq. LRI);
+ *    V: [n_abf(row)][n_abf(col)];  D and Sigma: [n_ao(row)][n_ao(col)].
+ *    Blocks are translation invariant: the block between X in cell R1 and Y in
+ *    cell R2 is the stored (X, Y, R2 - R1).
+ *  - On-site pairs follow set semantics: a unit whose F is A itself (same atom,
+ *    same cell) is weighted 1/2, likewise G = B; on-site C blocks must be
+ *    symmetric in their two AO indices.
+ *  - "Kept" means bound > threshold; a threshold of 0 keeps every non-zero bound.
+ *  - Sigma is produced on the block pattern of D; contributions to blocks
+ *    outside that pattern are not formed.
+ *
+ * Ownership: inputs are borrowed for the duration of a call.  hfx_plan_create
+ * copies what it needs (C, V, the D pattern) into device memory it owns;
+ * hfx_build reads D and writes Sigma, stream-ordered on the plan's stream.
+ *
+ * Errors: every function returns an hfx_status and never aborts; the message
+ * of the last failure on the calling thread is in hfx_last_error().  After an
+ * error the outputs are unspecified; the plan stays usable except after
+ * HFX_ERR_HIP, which poisons it (every later call returns HFX_ERR_STATE).
+ *
+ * Thread safety: a plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef HFX_H
+#define HFX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HFX_ABI_VERSION 1
+
+typedef enum {
+  HFX_OK = 0,
+  HFX_ERR_ARG = 1,         /* NULL pointer, bad count, non-finite or negative threshold      */
+  HFX_ERR_SHAPE = 2,       /* block index out of range, inconsistent sizes, duplicate blocks  */
+  HFX_ERR_SYMMETRY = 3,    /* V(A,B,R) != V(B,A,-R)^T, or a non-symmetric on-site C block     */
+  HFX_ERR_OOM = 4,         /* device allocation failed or exceeds max_device_bytes            */
+  HFX_ERR_HIP = 5,         /* a HIP runtime call failed (plan is poisoned)                    */
+  HFX_ERR_STATE = 6,       /* D does not match the plan's pattern, or poisoned plan           */
+  HFX_ERR_UNSUPPORTED = 7  /* option value not implemented                                    */
+} hfx_status;
+
+typedef struct {
+  int32_t n_ao;  /* atomic orbitals per atom of this species  (n_phi)                         */
+  int32_t n_abf; /* auxiliary basis functions per atom         (n_P)                          */
+} hfx_species;
+
+typedef struct {             /* one periodic home cell                                      */
+  int32_t n_atoms;
+  double lattice[9];         /* rows a1, a2, a3 (bohr)                                       */
+  const double *pos;         /* n_atoms*3 cartesian positions (bohr), host                   */
+  const int32_t *species;    /* n_atoms species indices, host                                */
+  int32_t n_species;
+  const hfx_species *sp;     /* n_species entries, host                                      */
+} hfx_cell;
+
+typedef struct {             /* block-sparse periodic tensor                                 */
+  int64_t n_blocks;
+  const int32_t *row;        /* n_blocks home-cell row atoms, host                           */
+  const int32_t *col;        /* n_blocks home-cell index of the column atom, host            */
+  const int32_t *R;          /* n_blocks*3 lattice vector of the column atom, host           */
+  const int64_t *off;        /* n_blocks start of each block in data (elements), host; blocks
+                                may alias each other (read-only)                             */
+  const double *data;        /* FP64 block data, host (on_device=0) or device (on_device=1)  */
+  int32_t on_device;
+} hfx_blocks;
+
+typedef struct {             /* Sec. III B and III C; 0 keeps every non-zero bound           */
+  double eps_C;              /* drop C blocks with max-abs <= eps_C                          */
+  double eps_V;              /* drop V blocks with max-abs <= eps_V                          */
+  double eps_D;              /* drop D blocks with max-abs <= eps_D (per build)              */
+  double eps_cs_eri;         /* keep a quartet iff Q_AF * Q_BG > eps_cs_eri                  */
+  double eps_cs_mat;         /* keep a unit iff each of the three bounds > eps_cs_mat        */
+} hfx_thresholds;
+
+/* precision of the block contractions; screening bounds, accumulation into
+ * Sigma and the energy are FP64 in every mode */
+#define HFX_PREC_FP64 0     /* every contraction in FP64                                   */
+#define HFX_PREC_FP32 1     /* every contraction on FP32 MFMA, FP64 accumulation           */
+#define HFX_PREC_TIERED 2   /* per unit: FP64 if its bound > tier_tau, else FP32 MFMA      */
+#define HFX_PREC_BF16X3 3   /* split-BF16x3 MFMA for units with bound <= tier_tau_bf, FP32 /
+                               FP64 tiers above it                                          */
+
+#define HFX_SCREEN_PRE 1u    /* block max-abs pre-screening of C, V, D                     */
+#define HFX_SCREEN_CS_ERI 2u /* CS-ERI quartet test                                        */
+#define HFX_SCREEN_CS1 4u    /* CS-matrix stage 1: sqrt||CC+|| sqrt||VV+|| sqrt||CC+|| sqrt||DD+|| */
+#define HFX_SCREEN_CS2 8u    /* CS-matrix stage 2: sqrt||CC+|| ||VC|| sqrt||DD+||          */
+#define HFX_SCREEN_CS3 16u   /* CS-matrix stage 3: ||C|| ||(VC)D||                         */
+#define HFX_SCREEN_ALL 31u
+
+#define HFX_SCHED_PLAN 0    /* work items in plan order                                    */
+#define HFX_SCHED_LPT 1     /* longest-processing-time first on the screened unit counts   */
+#define HFX_SCHED_MLP 2     /* order by the learned cost model (mlp_weights)               */
+
+typedef struct {
+  int32_t precision;          /* HFX_PREC_*                                                 */
+  uint32_t stages;            /* HFX_SCREEN_* bitmask; 0 means HFX_SCREEN_ALL               */
+  double tier_tau;            /* TIERED / BF16X3: units with bound <= tier_tau leave FP64   */
+  double tier_tau_bf;         /* BF16X3: units with bound <= tier_tau_bf use split-BF16x3   */
+  int32_t scheduler;          /* HFX_SCHED_*                                                */
+  const char *mlp_weights;    /* file written by the scheduler trainer, or NULL             */
+  void *stream;               /* hipStream_t for plan-time and build work; NULL = default   */
+  const int32_t *home_subset; /* global atom ids (atom i of cell c is atom_offset(c)+i)
+                                 whose <A,B> work items are built; NULL = all              */
+  int32_t n_home_subset;
+  uint64_t max_device_bytes;  /* 0 = unlimited; else plan creation fails with HFX_ERR_OOM
+                                 when its device footprint would exceed this               */
+  int32_t n_slots;            /* persistent workgroups (0 = automatic)                      */
+} hfx_options;
+
+typedef struct {               /* filled by hfx_build when non-NULL (synchronises)          */
+  int64_t candidates;          /* (A,B,F,G) grid points visited                             */
+  int64_t kept_cs_eri;         /* quartets passing CS-ERI                                   */
+  int64_t kept[3][4];          /* [stage 1..3][term 1..4] units surviving each stage        */
+  int64_t items;               /* <A,B> work items                                          */
+  int64_t g_alive;             /* (A,B,G) triples whose Y = V C was formed                  */
+  double flops_contract;       /* FP64-equivalent FLOPs of the contractions as executed     */
+  double flops_paper;          /* FLOPs of the same kept units counted per unit as in
+                                  Algorithm 3 (Y once per (A,B,G), T3/T4 once per G)        */
+  double flops_tier[3];        /* executed contraction FLOPs in FP64 / FP32 / BF16x3        */
+  double ms_total;             /* device time of the build (events on the plan stream)      */
+  double ms_main;              /* device time of the main persistent kernel                 */
+} hfx_build_stats;
+
+typedef struct hfx_plan hfx_plan;
+
+/* Per-geometry set-up (Algorithm 5, "Calculate C and V"): validates the
+ * inputs, pre-screens C and V, computes the block norms of the Cauchy-Schwarz
+ * bounds and the CS-ERI factors Q_AF = sqrt(max_{a,f} (Aa Ff|Aa Ff)), builds
+ * the neighbour lists N[A] (Sec. III B 1) and the <A,B> work items, and
+ * copies everything to device memory owned by the plan.
+ *   n_cells     >= 1 independent cells, built together in one launch
+ *   cells       n_cells cell descriptions
+ *   C, V        n_cells block sets each (data host or device)
+ *   D_pattern   n_cells D block structures (row/col/R/off; data may be NULL)
+ *   th          thresholds; opt: options (NULL = defaults)
+ *   out         receives the plan
+ * Synchronises before returning. */
+hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blocks *C, const hfx_blocks *V,
+                           const hfx_blocks *D_pattern, const hfx_thresholds *th, const hfx_options *opt,
+                           hfx_plan **out);
+
+/* Layout of Sigma for one cell: the D pattern's row/col/R with compact
+ * offsets (running sum of n_ao(row)*n_ao(col) in block order).  The arrays
+ * are owned by the plan (host memory, valid until hfx_plan_destroy);
+ * layout->data is NULL.  *n_elements receives the FP64 count of the cell's
+ * Sigma buffer. */
+hfx_status hfx_sigma_layout(const hfx_plan *plan, int32_t cell, hfx_blocks *layout, int64_t *n_elements);
+
+/* Per-SCF-step build (Algorithm 5, "Calculate exact-exchange"):
+ *   D      n_cells density matrices with the plan's pattern: n_blocks and the
+ *          block shapes must match; off (if non-NULL) must equal the
+ *          pattern's off, else HFX_ERR_STATE.  data host or device.
+ *   sigma  n_cells device buffers of hfx_sigma_layout's size, fully overwritten
+ *   stats  optional; when non-NULL the call synchronises and fills it
+ * Stream-ordered on opt.stream; returns before completion unless stats is
+ * requested.  D is read during the call's stream work; keep it alive until
+ * the stream has passed this build. */
+hfx_status hfx_build(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, hfx_build_stats *stats);
+
+/* E_x = 1/2 <D, Sigma^X> per cell with compensated FP64 summation over the
+ * D pattern; D as in hfx_build, sigma device buffers from hfx_build.
+ * e_x: n_cells host doubles.  Synchronises. */
+hfx_status hfx_energy(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, double *e_x);
+
+/* Per-item cost labels of the last build, for scheduler training: for each
+ * work item in plan order, the cycle count of its main-kernel pass and the
+ * number of kept units per term.  cycles: n_items int64, units: n_items*4
+ * int64 (host).  Synchronises. */
+hfx_status hfx_item_profile(hfx_plan *plan, int64_t *n_items, int64_t *cycles, int64_t *units);
+
+void hfx_plan_destroy(hfx_plan *plan);
+const char *hfx_last_error(void);
+int32_t hfx_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFX_H */

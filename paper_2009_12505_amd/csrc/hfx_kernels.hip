@@ -1,0 +1,1082 @@
+// Device kernels of the periodic exchange-matrix build (gfx950).
+//
+// The main kernel is persistent: each workgroup takes <A,B> work items
+// (Algorithm 2) from a global ticket in schedule order and evaluates all
+// four Htilde pieces of eq. HFX_split for every (F,G) neighbour pair of the
+// item, with the screening of Algorithm 5.  Per item, in order:
+//
+//   screen   CS-ERI and CS-matrix stage 1 for each (F,G,term) (Alg. 4 first test)
+//   G side   Y_G = V_AB C_BG (Alg. 3), its slice norms (stage 2), T3_G = Y D_AG and
+//            T4_G = Y D_AB (both independent of F), their norms (stage 3 of terms
+//            3, 4), and the Gram matrices of Y that give the stage-3 norms of terms
+//            1 and 2 without forming T1, T2
+//   masks    stages 2 and 3 for each surviving unit
+//   GEMM-R   terms 3 and 4:  C_A^T [T4_G | T3_G]  over the concatenated (F,f) x (G,.)
+//            grid, masked per (F,G) block; term 4 goes straight to Sigma(F,G),
+//            term 3 is summed over G before it goes to Sigma(F,B)
+//   GEMM-L   terms 1 and 2:  C_A [w D_FG | w D_FB] (the C D products of all kept
+//            units), contracted with Y_G in the epilogue: term 1 summed over F and
+//            G into Sigma(A,B), term 2 summed over F into Sigma(A,G)
+//
+// Contractions use the FP64 matrix cores (v_mfma_f64_16x16x4f64), one 16x16
+// output tile per wave at a time; a tile whose (F,G) blocks are all screened
+// out is skipped.  Sigma accumulation is FP64 (global atomics).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hfx_internal.h"
+
+namespace hfx {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 512;
+constexpr int NW = NT / 64;
+constexpr int MAXNB = 256;
+constexpr int MAXN = 32;
+
+// v_mfma_f64_16x16x4f64 lane layout (gfx950): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; element e of the result holds D[l/16 + 4e][l%16].
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int lookup_d(const DevPlan &P, int row, int col, int32_t R) {
+  const int c = P.cell_of[row];
+  const int n = P.cell_natoms[c];
+  const int t = P.ptab_off[c] + P.local_of[row] * n + P.local_of[col];
+  const int s = P.pstart[t], e = s + P.pcount[t];
+  for (int q = s; q < e; ++q)
+    if (P.dsort_R[q] == R) return P.dsort_id[q];
+  return -1;
+}
+
+// term bits of the per-(F,G) masks
+constexpr uint8_t kT1 = 1, kT2 = 2, kT3 = 4, kT4 = 8, kCsOk = 16, kPend1 = 32;
+
+struct ItemLds {
+  int A, B, rb, PA, PB, na, nb, nF, nG, nGa, MR, NR, J;
+  int dAB;
+  int okAB;  // D_AB usable as operand (exists and kept)
+  double gV;
+  long long voff;
+  int cA, cB;  // first kept C block of A, of B
+  // F side (i < nF)
+  int f_atom[MAXNB], f_R[MAXNB], f_n[MAXNB], f_row0[MAXNB + 1], f_dFB[MAXNB];
+  long long f_dFBoff[MAXNB];
+  long long f_coff[MAXNB];
+  double f_gA[MAXNB], f_gF[MAXNB], f_nA[MAXNB], f_nF[MAXNB], f_Q[MAXNB];
+  uint8_t f_on[MAXNB];
+  // G side (j < nG)
+  int g_atom[MAXNB], g_R[MAXNB], g_n[MAXNB], g_dAG[MAXNB];
+  long long g_dAGoff[MAXNB];
+  long long g_coff[MAXNB];
+  double g_gA[MAXNB], g_gF[MAXNB], g_Q[MAXNB];
+  uint8_t g_on[MAXNB];
+  int g_alive[MAXNB];
+  // alive G (jj < nGa)
+  short a_j[MAXNB];
+  int a_col0[MAXNB + 1];
+  int a_y[MAXNB], a_t3[MAXNB], a_t4[MAXNB], a_n1[MAXNB], a_m2[MAXNB];
+  double a_Yb[MAXNB], a_Yg[MAXNB], a_T3n[MAXNB], a_T4n[MAXNB];
+  double H1[MAXN * MAXN];
+  double DAB[MAXN * MAXN];
+  double DAG[MAXN * MAXN];
+  double sq[2 * MAXN];
+  double tile[NW][256];
+  unsigned long long cnt[kCntN];
+  int scratch_top;
+};
+
+struct KParams {
+  int rows_cap, cols_cap;  // sizes of the row/col decode tables (bytes) in dynamic LDS
+  int acc_doubles;         // per-wave accumulator (doubles) in dynamic LDS
+};
+
+// ---------------------------------------------------------------------------------------------
+// screen: CS-ERI + stage 1 on the F x G grid
+__device__ void phase_screen(const DevPlan &P, ItemLds &L, int *dfg, uint8_t *mask) {
+  const int tid = threadIdx.x;
+  const int nF = L.nF, nG = L.nG;
+  const double eps = P.eps_mat, eps_eri = P.eps_eri;
+  const bool use_eri = P.stages & kCsEri, use1 = P.stages & kCs1;
+  unsigned long long c_eri = 0, c1[4] = {0, 0, 0, 0};
+  for (int p = tid; p < nF * nG; p += NT) {
+    const int i = p / nG, j = p - i * nG;
+    const int dFG = lookup_d(P, L.f_atom[i], L.g_atom[j], r_sub(L.g_R[j], L.f_R[i]));
+    dfg[p] = dFG;
+    uint8_t bits = 0;
+    if (!use_eri || L.f_Q[i] * L.g_Q[j] > eps_eri) {
+      bits = kCsOk;
+      ++c_eri;
+      // term 1: D_FG operand, target (A,B)
+      if (dFG >= 0 && P.keepD[dFG] && L.dAB >= 0) {
+        if (!use1 || L.f_gA[i] * L.gV * L.g_gA[j] * P.gD[dFG] > eps) bits |= kT1;
+      }
+      // term 2: D_FB operand, target (A,G)
+      const int dFB = L.f_dFB[i];
+      if (dFB >= 0 && P.keepD[dFB] && L.g_dAG[j] >= 0) {
+        if (!use1 || L.f_gA[i] * L.gV * L.g_gF[j] * P.gD[dFB] > eps) bits |= kT2;
+      }
+      // term 3: D_AG operand, target (F,B)
+      const int dAG = L.g_dAG[j];
+      if (dAG >= 0 && P.keepD[dAG] && dFB >= 0) {
+        if (!use1 || L.f_gF[i] * L.gV * L.g_gA[j] * P.gD[dAG] > eps) bits |= kT3;
+      }
+      // term 4: D_AB operand, target (F,G)
+      if (L.okAB && dFG >= 0) {
+        if (!use1 || L.f_gF[i] * L.gV * L.g_gF[j] * P.gD[L.dAB] > eps) bits |= kT4;
+      }
+      for (int t = 0; t < 4; ++t) c1[t] += (bits >> t) & 1;
+      if (bits & 15) L.g_alive[j] = 1;
+    }
+    mask[p] = bits;
+  }
+  atomicAdd(&L.cnt[kCntCsEri], c_eri);
+  for (int t = 0; t < 4; ++t)
+    if (c1[t]) atomicAdd(&L.cnt[kCntKept + t], c1[t]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// G side for one alive G: Y = V_AB C_BG, norms, T3, T4, Gram matrices
+__device__ void phase_gside_one(const DevPlan &P, ItemLds &L, double *slot, int jj) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int j = L.a_j[jj];
+  const int PA = L.PA, PB = L.PB, na = L.na, nb = L.nb, ng = L.g_n[j];
+  const int N = nb * ng;
+  const double *V = P.Vbuf + L.voff;
+  const double *C = P.Cbuf + L.g_coff[j];
+  double *Y = slot + L.a_y[jj];
+  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]
+  {
+    const int mt = (PA + 15) >> 4, nt = (N + 15) >> 4;
+    for (int t = wave; t < mt * nt; t += NW) {
+      const int m0 = (t / nt) << 4, n0 = (t % nt) << 4;
+      const int row = m0 + (lane & 15), col = n0 + (lane & 15), kk = lane >> 4;
+      d4 acc = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < PB; k0 += 4) {
+        const int k = k0 + kk;
+        const double a = (row < PA && k < PB) ? V[row * PB + k] : 0.0;
+        const double b = (k < PB && col < N) ? C[(long long)k * N + col] : 0.0;
+        acc = mfma64(a, b, acc);
+      }
+      const int c = n0 + (lane & 15);
+      for (int e = 0; e < 4; ++e) {
+        const int r = m0 + (lane >> 4) + 4 * e;
+        if (r < PA && c < N) Y[(long long)r * N + c] = acc[e];
+      }
+    }
+  }
+  // D_AG for this G
+  const int dAG = L.g_dAG[j];
+  const bool okAG = dAG >= 0 && P.keepD[dAG];
+  if (okAG)
+    for (int q = tid; q < na * ng; q += NT) L.DAG[q] = P.Dbuf[P.d_off[dAG] + q];
+  if (tid < 2 * MAXN) L.sq[tid] = 0.0;
+  __syncthreads();
+  // Gram matrices: N1[b][g][g'] = sum_al Y[al][b][g] Y[al][b][g'];  M2[g][b][b'] = sum_al Y[al][b][g] Y[al][b'][g]
+  double *N1 = slot + L.a_n1[jj];
+  double *M2 = slot + L.a_m2[jj];
+  for (int q = tid; q < nb * ng * ng; q += NT) {
+    const int b = q / (ng * ng), g = (q / ng) % ng, g2 = q % ng;
+    double s = 0;
+    for (int al = 0; al < PA; ++al) s += Y[(long long)al * N + b * ng + g] * Y[(long long)al * N + b * ng + g2];
+    N1[q] = s;
+  }
+  for (int q = tid; q < ng * nb * nb; q += NT) {
+    const int g = q / (nb * nb), b = (q / nb) % nb, b2 = q % nb;
+    double s = 0;
+    for (int al = 0; al < PA; ++al) s += Y[(long long)al * N + b * ng + g] * Y[(long long)al * N + b2 * ng + g];
+    M2[q] = s;
+  }
+  // T4[al*na+a][g] = sum_b Y[al][b][g] D_AB[a][b]
+  if (L.okAB) {
+    double *T4 = slot + L.a_t4[jj];
+    for (int q = tid; q < PA * na * ng; q += NT) {
+      const int al = q / (na * ng), a = (q / ng) % na, g = q % ng;
+      double s = 0;
+      for (int b = 0; b < nb; ++b) s += Y[(long long)al * N + b * ng + g] * L.DAB[a * nb + b];
+      T4[q] = s;
+      atomicAdd(&L.sq[g], s * s);
+    }
+  }
+  // T3[al*na+a][b] = sum_g Y[al][b][g] D_AG[a][g]
+  if (okAG) {
+    double *T3 = slot + L.a_t3[jj];
+    for (int q = tid; q < PA * na * nb; q += NT) {
+      const int al = q / (na * nb), a = (q / nb) % na, b = q % nb;
+      double s = 0;
+      for (int g = 0; g < ng; ++g) s += Y[(long long)al * N + b * ng + g] * L.DAG[a * ng + g];
+      T3[q] = s;
+      atomicAdd(&L.sq[MAXN + b], s * s);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double yb = 0, yg = 0, t3 = 0, t4 = 0;
+    for (int b = 0; b < nb; ++b) {
+      double s = 0;
+      for (int g = 0; g < ng; ++g) s += N1[(b * ng + g) * ng + g];
+      yb = fmax(yb, s);
+      t3 = fmax(t3, L.sq[MAXN + b]);
+    }
+    for (int g = 0; g < ng; ++g) {
+      double s = 0;
+      for (int b = 0; b < nb; ++b) s += M2[(g * nb + b) * nb + b];
+      yg = fmax(yg, s);
+      t4 = fmax(t4, L.sq[g]);
+    }
+    L.a_Yb[jj] = sqrt(yb);
+    L.a_Yg[jj] = sqrt(yg);
+    L.a_T3n[jj] = sqrt(t3);
+    L.a_T4n[jj] = sqrt(t4);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------------
+// masks: stages 2 and 3 for the stage-1 survivors of alive G's
+__device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, uint8_t *mask, double *E2) {
+  const int tid = threadIdx.x;
+  const int nb = L.nb;
+  const double eps = P.eps_mat;
+  const bool use2 = P.stages & kCs2, use3 = P.stages & kCs3;
+  // E2_i = D_FB^T D_FB  [b][b']
+  for (int q = tid; q < L.nF * nb * nb; q += NT) {
+    const int i = q / (nb * nb), b = (q / nb) % nb, b2 = q % nb;
+    const int dFB = L.f_dFB[i];
+    double s = 0;
+    if (dFB >= 0) {
+      const double *D = P.Dbuf + L.f_dFBoff[i];
+      const int nf = L.f_n[i];
+      for (int f = 0; f < nf; ++f) s += D[f * nb + b] * D[f * nb + b2];
+    }
+    E2[q] = s;
+  }
+  __syncthreads();
+  unsigned long long c2[4] = {0, 0, 0, 0}, c3[4] = {0, 0, 0, 0};
+  for (int p = tid; p < L.nF * L.nGa; p += NT) {
+    const int i = p / L.nGa, jj = p - i * L.nGa;
+    const int j = L.a_j[jj];
+    const int q = i * L.nG + j;
+    uint8_t bits = mask[q];
+    if (!(bits & 15)) continue;
+    const int ng = L.g_n[j];
+    (void)ng;
+    // term 1 (stage 3 is evaluated below, one wave per unit)
+    if (bits & kT1) {
+      const int d = dfg[q];
+      const bool keep = !use2 || L.f_gA[i] * L.a_Yb[jj] * P.gD[d] > eps;
+      if (keep) {
+        ++c2[0];
+        if (use3)
+          bits |= kPend1;
+        else
+          ++c3[0];
+      } else {
+        bits &= ~kT1;
+      }
+    }
+    // term 2
+    if (bits & kT2) {
+      const int d = L.f_dFB[i];
+      bool keep = !use2 || L.f_gA[i] * L.a_Yg[jj] * P.gD[d] > eps;
+      if (keep) {
+        ++c2[1];
+        if (use3) {
+          // ||T2[:,:,g]||^2 = sum_{b,b'} (D^T D)[b][b'] M2[g][b][b'],  D = D_FB [f][b]
+          const double *M2 = slot + L.a_m2[jj];
+          const double *E = E2 + i * nb * nb;
+          double tmax = 0;
+          for (int g = 0; g < ng; ++g) {
+            double s = 0;
+            for (int b = 0; b < nb * nb; ++b) s += E[b] * M2[g * nb * nb + b];
+            tmax = fmax(tmax, s);
+          }
+          keep = L.f_nA[i] * sqrt(fmax(tmax, 0.0)) > eps;
+        }
+        if (keep) ++c3[1];
+      }
+      if (!keep) bits &= ~kT2;
+    }
+    // term 3
+    if (bits & kT3) {
+      bool keep = !use2 || L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]] > eps;
+      if (keep) {
+        ++c2[2];
+        if (use3) keep = L.f_nF[i] * L.a_T3n[jj] > eps;
+        if (keep) ++c3[2];
+      }
+      if (!keep) bits &= ~kT3;
+    }
+    // term 4
+    if (bits & kT4) {
+      bool keep = !use2 || L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB] > eps;
+      if (keep) {
+        ++c2[3];
+        if (use3) keep = L.f_nF[i] * L.a_T4n[jj] > eps;
+        if (keep) ++c3[3];
+      }
+      if (!keep) bits &= ~kT4;
+    }
+    mask[q] = bits;
+  }
+  __syncthreads();
+  // term 1, stage 3:  ||T1[:,:,b]||^2 = sum_{g,g'} (D^T D)[g][g'] N1[b][g][g'],  D = D_FG [f][g]
+  // (the Gram form of ||(V C) D||, so T1 itself is never formed for a dropped unit)
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int p = wave; p < L.nF * L.nGa; p += NW) {
+      const int i = p / L.nGa, jj = p - i * L.nGa;
+      const int j = L.a_j[jj];
+      const int q = i * L.nG + j;
+      const uint8_t bits = mask[q];
+      if (!(bits & kPend1)) continue;
+      const int ng = L.g_n[j], nf = L.f_n[i];
+      const double *D = P.Dbuf + P.d_off[dfg[q]];
+      const double *N1 = slot + L.a_n1[jj];
+      double e[16];
+      int ne = 0;
+      for (int x = lane; x < ng * ng && ne < 16; x += 64, ++ne) {
+        const int g = x / ng, g2 = x - g * ng;
+        double s = 0;
+        for (int f = 0; f < nf; ++f) s += D[f * ng + g] * D[f * ng + g2];
+        e[ne] = s;
+      }
+      double tmax = 0;
+      for (int b = 0; b < nb; ++b) {
+        double s = 0;
+        int k = 0;
+        for (int x = lane; x < ng * ng && k < 16; x += 64, ++k) s += e[k] * N1[b * ng * ng + x];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        tmax = fmax(tmax, s);
+      }
+      const bool keep = L.f_nA[i] * sqrt(fmax(tmax, 0.0)) > eps;
+      if (lane == 0) {
+        mask[q] = keep ? (uint8_t)(bits & ~kPend1) : (uint8_t)(bits & ~(kPend1 | kT1));
+        if (keep) ++c3[0];
+      }
+    }
+  }
+  for (int t = 0; t < 4; ++t) {
+    if (c2[t]) atomicAdd(&L.cnt[kCntKept + 4 + t], c2[t]);
+    if (c3[t]) atomicAdd(&L.cnt[kCntKept + 8 + t], c3[t]);
+  }
+}
+
+__device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
+  return (L.f_on[i] ? 0.5 : 1.0) * (L.g_on[j] ? 0.5 : 1.0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// GEMM-R: terms 3 and 4.  Rows (F,f), K = (alpha,a), columns (G, [g | b]).
+__device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
+                             const uint8_t *row2i, const short *col2jj, double *accw, int acc_doubles) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int K = L.PA * L.na, nb = L.nb;
+  const int mt = (L.MR + 15) >> 4, nt = (L.NR + 15) >> 4;
+  double *acc3 = accw + wave * acc_doubles;  // [16 rows][b]
+  unsigned long long nmfma = 0;
+  for (int rt = wave; rt < mt; rt += NW) {
+    for (int q = lane; q < 16 * MAXN; q += 64) acc3[q] = 0.0;
+    bool any3 = false;
+    // this lane's A row
+    const int ra = (rt << 4) + (lane & 15);
+    const int ia = ra < L.MR ? row2i[ra] : 0;
+    const int fa = ra - L.f_row0[ia];
+    const double *Arow = P.Cbuf + L.f_coff[ia] + fa;  // element k at Arow[k * nf]
+    const int nfa = L.f_n[ia];
+    for (int ct = 0; ct < nt; ++ct) {
+      // exact skip test over the 256 elements of the tile
+      bool need = false;
+      {
+        const int r = (rt << 4) + (lane & 15);
+        for (int e = 0; e < 4; ++e) {
+          const int c = (ct << 4) + ((lane >> 4) << 2) + e;
+          if (r < L.MR && c < L.NR) {
+            const int i = row2i[r], jj = col2jj[c];
+            const int j = L.a_j[jj];
+            const int cc = c - L.a_col0[jj];
+            const uint8_t bits = mask[i * L.nG + j];
+            need |= (cc < L.g_n[j]) ? (bits & kT4) != 0 : (bits & kT3) != 0;
+          }
+        }
+      }
+      if (!__any(need)) continue;
+      // this lane's B column
+      const int cb = (ct << 4) + (lane & 15);
+      const double *Bcol = nullptr;
+      int ldb = 0;
+      if (cb < L.NR) {
+        const int jj = col2jj[cb], j = L.a_j[jj];
+        const int cc = cb - L.a_col0[jj], ng = L.g_n[j];
+        if (cc < ng) {
+          Bcol = slot + L.a_t4[jj] + cc;
+          ldb = ng;
+        } else {
+          Bcol = slot + L.a_t3[jj] + (cc - ng);
+          ldb = nb;
+        }
+      }
+      d4 acc = {0, 0, 0, 0};
+      const int kk = lane >> 4;
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + kk;
+        const double a = (ra < L.MR && k < K) ? Arow[(long long)k * nfa] : 0.0;
+        const double b = (Bcol && k < K) ? Bcol[(long long)k * ldb] : 0.0;
+        acc = mfma64(a, b, acc);
+      }
+      nmfma += (K + 3) >> 2;
+      // epilogue
+      const int c = (ct << 4) + (lane & 15);
+      if (c < L.NR) {
+        const int jj = col2jj[c], j = L.a_j[jj];
+        const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+        for (int e = 0; e < 4; ++e) {
+          const int rl = (lane >> 4) + 4 * e;
+          const int r = (rt << 4) + rl;
+          if (r >= L.MR) continue;
+          const int i = row2i[r], f = r - L.f_row0[i];
+          const uint8_t bits = mask[i * L.nG + j];
+          const double w = unit_weight(L, i, j);
+          if (cc < ng) {
+            if (bits & kT4) {
+              const int d = dfg[i * L.nG + j];
+              atomicAdd(P.Sbuf + P.d_off[d] + f * ng + cc, -w * acc[e]);
+            }
+          } else if (bits & kT3) {
+            atomicAdd(&acc3[rl * MAXN + (cc - ng)], -w * acc[e]);
+            any3 = true;
+          }
+        }
+      }
+    }
+    // flush term 3: Sigma(F,B)[f][b]
+    if (__any(any3)) {
+      for (int q = lane; q < 16 * nb; q += 64) {
+        const int rl = q / nb, b = q - rl * nb;
+        const int r = (rt << 4) + rl;
+        if (r >= L.MR) continue;
+        const double v = acc3[rl * MAXN + b];
+        if (v != 0.0) {
+          const int i = row2i[r], f = r - L.f_row0[i];
+          atomicAdd(P.Sbuf + L.f_dFBoff[i] + f * nb + b, v);
+        }
+      }
+    }
+  }
+  if (lane == 0 && nmfma) atomicAdd(&L.cnt[kCntMfmaR], nmfma);
+}
+
+// ---------------------------------------------------------------------------------------------
+// GEMM-L: terms 1 and 2.  Rows (alpha,a), K = (F,f), columns (G, [g | b]).
+//   P[(al,a)][(G,g)] = sum_{F,f} C_AF[al][a][f] w D_FG[f][g]   (term 1, kept units only)
+//   P[(al,a)][(G,b)] = sum_{F,f} C_AF[al][a][f] w D_FB[f][b]   (term 2, kept units only)
+//   H1[a][b]  += sum_{al,G,g} P[(al,a)][(G,g)] Y_G[al][b][g]      -> Sigma(A,B)
+//   H2_G[a][g] = sum_{al,b}  P[(al,a)][(G,b)] Y_G[al][b][g]      -> Sigma(A,G)
+__device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
+                             const uint8_t *row2i, const short *col2jj, double *accw, int acc_doubles) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = L.PA * L.na, na = L.na, nb = L.nb, nF = L.nF;
+  const int mt = (M + 15) >> 4, nt = (L.NR + 15) >> 4;
+  double *acc2 = accw + wave * acc_doubles;  // [jj - jj0][a][g]
+  double *tl = L.tile[wave];
+  unsigned long long nmfma = 0;
+  for (int ct = wave; ct < nt; ct += NW) {
+    const int c0 = ct << 4;
+    const int c1 = min(c0 + 16, L.NR);
+    const int jj0 = col2jj[c0], jj1 = col2jj[c1 - 1];
+    // which halves of which G appear in this column tile
+    // F set: i with any kept term-1 unit (g-half present) or term-2 unit (b-half present)
+    unsigned long long fset[4] = {0, 0, 0, 0};
+    for (int base = 0; base < nF; base += 64) {
+      const int i = base + lane;
+      bool hit = false;
+      if (i < nF) {
+        for (int jj = jj0; jj <= jj1; ++jj) {
+          const int j = L.a_j[jj];
+          const int g0 = L.a_col0[jj], gb = g0 + L.g_n[j], g1 = L.a_col0[jj + 1];
+          const bool hasg = max(c0, g0) < min(c1, gb);
+          const bool hasb = max(c0, gb) < min(c1, g1);
+          const uint8_t bits = mask[i * L.nG + j];
+          hit |= (hasg && (bits & kT1)) || (hasb && (bits & kT2));
+        }
+      }
+      fset[base >> 6] = __ballot(hit);
+    }
+    if (!(fset[0] | fset[1] | fset[2] | fset[3])) continue;
+    const int nj = jj1 - jj0 + 1;
+    for (int q = lane; q < nj * na * MAXN; q += 64) acc2[q] = 0.0;
+    // this lane's B column
+    const int cb = c0 + (lane & 15);
+    int jjb = 0, jb = 0, ccb = 0, ngb = 0;
+    bool colok = cb < L.NR;
+    if (colok) {
+      jjb = col2jj[cb];
+      jb = L.a_j[jjb];
+      ccb = cb - L.a_col0[jjb];
+      ngb = L.g_n[jb];
+    }
+    bool any1 = false, any2 = false;
+    for (int rt = 0; rt < mt; ++rt) {
+      const int r = (rt << 4) + (lane & 15);  // A row (al,a)
+      const bool rowok = r < M;
+      d4 acc = {0, 0, 0, 0};
+      int kdone = 0;
+      bool did = false;
+      for (int w64 = 0; w64 < 4; ++w64) {
+        unsigned long long m = fset[w64];
+        while (m) {
+          const int i = (w64 << 6) + __builtin_ctzll(m);
+          m &= m - 1;
+          const int kb = L.f_row0[i], ke = L.f_row0[i + 1];
+          int k0 = max(kb & ~3, kdone);
+          for (; k0 < ke; k0 += 4) {
+            const int k = k0 + (lane >> 4);
+            double a = 0.0, b = 0.0;
+            if (k < L.MR) {
+              const int ik = row2i[k], f = k - L.f_row0[ik];
+              if (rowok) a = P.Cbuf[L.f_coff[ik] + (long long)r * L.f_n[ik] + f];
+              if (colok) {
+                const uint8_t bits = mask[ik * L.nG + jb];
+                const double w = unit_weight(L, ik, jb);
+                if (ccb < ngb) {
+                  if (bits & kT1) b = w * P.Dbuf[P.d_off[dfg[ik * L.nG + jb]] + f * ngb + ccb];
+                } else if (bits & kT2) {
+                  b = w * P.Dbuf[L.f_dFBoff[ik] + f * nb + (ccb - ngb)];
+                }
+              }
+            }
+            acc = mfma64(a, b, acc);
+            ++nmfma;
+          }
+          kdone = max(kdone, k0);
+          did = true;
+        }
+      }
+      if (!did) continue;
+      // stage the tile in LDS: tl[row][col]
+      for (int e = 0; e < 4; ++e) tl[((lane >> 4) + 4 * e) * 16 + (lane & 15)] = acc[e];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      // epilogue: 16 rows x MAXN outputs
+      for (int q = lane; q < 16 * MAXN; q += 64) {
+        const int rl = q / MAXN, o = q - rl * MAXN;
+        const int rr = (rt << 4) + rl;
+        if (rr >= M) continue;
+        const int al = rr / na, a = rr - al * na;
+        double s1 = 0.0;
+        int jcur = -1;
+        double s2 = 0.0;
+        for (int cl = 0; cl < c1 - c0; ++cl) {
+          const int c = c0 + cl;
+          const int jj = col2jj[c], j = L.a_j[jj];
+          const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+          const double pv = tl[rl * 16 + cl];
+          if (pv == 0.0) continue;
+          const double *Y = slot + L.a_y[jj] + (long long)al * nb * ng;
+          if (cc < ng) {
+            if (o < nb) s1 += pv * Y[o * ng + cc];
+          } else {
+            if (jj != jcur) {
+              if (jcur >= 0 && s2 != 0.0) atomicAdd(&acc2[((jcur - jj0) * na + a) * MAXN + o], s2);
+              jcur = jj;
+              s2 = 0.0;
+            }
+            if (o < ng) s2 += pv * Y[(cc - ng) * ng + o];
+          }
+        }
+        if (jcur >= 0 && s2 != 0.0) {
+          atomicAdd(&acc2[((jcur - jj0) * na + a) * MAXN + o], s2);
+          any2 = true;
+        }
+        if (s1 != 0.0) {
+          atomicAdd(&L.H1[a * MAXN + o], s1);
+          any1 = true;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    (void)any1;
+    // flush term 2 of this column tile: Sigma(A,G)[a][g]
+    if (__any(any2)) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      for (int q = lane; q < nj * na * MAXN; q += 64) {
+        const int jl = q / (na * MAXN), a = (q / MAXN) % na, g = q % MAXN;
+        const double v = acc2[q];
+        if (v == 0.0) continue;
+        const int j = L.a_j[jj0 + jl];
+        if (g < L.g_n[j]) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * L.g_n[j] + g, -v);
+      }
+    }
+  }
+  if (lane == 0 && nmfma) atomicAdd(&L.cnt[kCntMfmaL], nmfma);
+}
+
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
+  __shared__ ItemLds L;
+  extern __shared__ double dyn[];
+  uint8_t *row2i = reinterpret_cast<uint8_t *>(dyn);
+  short *col2jj = reinterpret_cast<short *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap);
+  double *accw = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap + 2 * kp.cols_cap);
+  __shared__ int s_item;
+  const int tid = threadIdx.x;
+  double *slot = P.scratch + (long long)blockIdx.x * P.slot_doubles;
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(P.ticket, 1u);
+    __syncthreads();
+    const int sidx = s_item;
+    if (sidx >= P.n_items) break;
+    const int item = P.order[sidx];
+    const long long t_start = wall_clock64();
+    const Item it = P.items[item];
+    if (tid < kCntN) L.cnt[tid] = 0;
+    if (tid == 0) {
+      L.A = it.A;
+      L.B = it.B;
+      L.rb = it.rb;
+      L.PA = P.nabf[it.A];
+      L.PB = P.nabf[it.B];
+      L.na = P.nao[it.A];
+      L.nb = P.nao[it.B];
+      L.cA = P.c_start[it.A];
+      L.cB = P.c_start[it.B];
+      L.nF = P.c_start[it.A + 1] - L.cA;
+      L.nG = P.c_start[it.B + 1] - L.cB;
+      L.gV = P.gV[it.vid];
+      L.voff = P.v_off[it.vid];
+      L.dAB = lookup_d(P, it.A, it.B, it.rb);
+      L.okAB = L.dAB >= 0 && P.keepD[L.dAB];
+    }
+    __syncthreads();
+    // F and G lists
+    for (int i = tid; i < L.nF; i += NT) {
+      const int cf = L.cA + i;
+      const int F = P.c_col[cf];
+      const int RF = P.c_R[cf];
+      L.f_atom[i] = F;
+      L.f_R[i] = RF;
+      L.f_n[i] = P.nao[F];
+      L.f_coff[i] = P.c_off[cf];
+      const CNorm cn = P.c_norm[cf];
+      L.f_gA[i] = cn.gA;
+      L.f_gF[i] = cn.gF;
+      L.f_nA[i] = cn.nA;
+      L.f_nF[i] = cn.nF;
+      L.f_Q[i] = cn.Q;
+      L.f_on[i] = (F == L.A && r_zero(RF));
+      const int d = lookup_d(P, F, L.B, r_sub(L.rb, RF));
+      L.f_dFB[i] = d;
+      L.f_dFBoff[i] = d >= 0 ? P.d_off[d] : 0;
+    }
+    for (int j = tid; j < L.nG; j += NT) {
+      const int cg = L.cB + j;
+      const int G = P.c_col[cg];
+      const int RG = r_add(L.rb, P.c_R[cg]);
+      L.g_atom[j] = G;
+      L.g_R[j] = RG;
+      L.g_n[j] = P.nao[G];
+      L.g_coff[j] = P.c_off[cg];
+      const CNorm cn = P.c_norm[cg];
+      L.g_gA[j] = cn.gA;
+      L.g_gF[j] = cn.gF;
+      L.g_Q[j] = cn.Q;
+      L.g_on[j] = (G == L.B && r_zero(P.c_R[cg]));
+      const int d = lookup_d(P, L.A, G, RG);
+      L.g_dAG[j] = d;
+      L.g_dAGoff[j] = d >= 0 ? P.d_off[d] : 0;
+      L.g_alive[j] = 0;
+    }
+    for (int q = tid; q < MAXN * MAXN; q += NT) L.H1[q] = 0.0;
+    if (L.okAB)
+      for (int q = tid; q < L.na * L.nb; q += NT) L.DAB[q] = P.Dbuf[P.d_off[L.dAB] + q];
+    __syncthreads();
+    if (tid == 0) {
+      int r0 = 0;
+      for (int i = 0; i < L.nF; ++i) {
+        L.f_row0[i] = r0;
+        r0 += L.f_n[i];
+      }
+      L.f_row0[L.nF] = r0;
+      L.MR = r0;
+    }
+    // slot scratch: dfg (int) and mask (bytes) over nF*nG, then E2, then per-G buffers
+    int *dfg = reinterpret_cast<int *>(slot);
+    const int nFG = L.nF * L.nG;
+    uint8_t *mask = reinterpret_cast<uint8_t *>(slot + ((nFG + 1) >> 1));
+    double *E2 = slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3);
+    double *gbase_d = E2 + L.nF * L.nb * L.nb;
+    __syncthreads();
+    phase_screen(P, L, dfg, mask);
+    __syncthreads();
+    // compact alive G and lay out their buffers
+    if (tid == 0) {
+      int n = 0, col = 0;
+      long long off = gbase_d - slot;
+      for (int j = 0; j < L.nG; ++j) {
+        if (!L.g_alive[j]) continue;
+        const int ng = L.g_n[j];
+        L.a_j[n] = (short)j;
+        L.a_col0[n] = col;
+        col += ng + L.nb;
+        const int ysz = L.PA * L.nb * ng;
+        L.a_y[n] = (int)off;
+        off += ysz;
+        L.a_t4[n] = (int)off;
+        off += L.PA * L.na * ng;
+        L.a_t3[n] = (int)off;
+        off += L.PA * L.na * L.nb;
+        L.a_n1[n] = (int)off;
+        off += L.nb * ng * ng;
+        L.a_m2[n] = (int)off;
+        off += ng * L.nb * L.nb;
+        ++n;
+      }
+      L.nGa = n;
+      L.a_col0[n] = col;
+      L.NR = col;
+      L.cnt[kCntCandidates] = (unsigned long long)L.nF * L.nG;
+      L.cnt[kCntG] = n;
+      L.scratch_top = (int)off;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < L.nGa; ++jj) phase_gside_one(P, L, slot, jj);
+    phase_masks(P, L, slot, dfg, mask, E2);
+    // decode tables
+    for (int r = tid; r < L.MR; r += NT) {
+      int lo = 0, hi = L.nF - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.f_row0[mid] <= r)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      row2i[r] = (uint8_t)lo;
+    }
+    for (int c = tid; c < L.NR; c += NT) {
+      int lo = 0, hi = L.nGa - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.a_col0[mid] <= c)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      col2jj[c] = (short)lo;
+    }
+    __syncthreads();
+    if (L.nGa > 0) {
+      phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, accw, kp.acc_doubles);
+      __syncthreads();
+      phase_gemm_l(P, L, slot, dfg, mask, row2i, col2jj, accw, kp.acc_doubles);
+    }
+    __syncthreads();
+    // flush term 1: Sigma(A,B)
+    if (L.dAB >= 0)
+      for (int q = tid; q < L.na * L.nb; q += NT) {
+        const int a = q / L.nb, b = q - a * L.nb;
+        const double v = L.H1[a * MAXN + b];
+        if (v != 0.0) atomicAdd(P.Sbuf + P.d_off[L.dAB] + q, -v);
+      }
+    if (tid < kCntN && L.cnt[tid]) atomicAdd(&P.counters[tid], L.cnt[tid]);
+    if (tid < 4) P.item_units[item * 4 + tid] = (int)L.cnt[kCntKept + 8 + tid];
+    if (tid == 0) P.item_cycles[item] = wall_clock64() - t_start;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// plan-time: C block norms (Sec. III C 1) -- one workgroup per kept C block
+__global__ __launch_bounds__(256) void k_cnorm(const double *__restrict__ Cbuf, const long long *__restrict__ c_off,
+                                               const int *__restrict__ c_row, const int *__restrict__ c_col,
+                                               const int *__restrict__ nao, const int *__restrict__ nabf, int nC,
+                                               CNorm *__restrict__ out) {
+  const int cb = blockIdx.x;
+  if (cb >= nC) return;
+  const int A = c_row[cb], F = c_col[cb];
+  const int P = nabf[A], na = nao[A], nf = nao[F];
+  const double *C = Cbuf + c_off[cb];
+  __shared__ double s_n[2][MAXN], s_g[2][MAXN];
+  const int tid = threadIdx.x;
+  if (tid < MAXN) {
+    s_n[0][tid] = s_n[1][tid] = 0;
+    s_g[0][tid] = s_g[1][tid] = 0;
+  }
+  __syncthreads();
+  // ||C[:,a,:]||^2 and ||C[:,:,f]||^2
+  for (int q = tid; q < na * nf; q += 256) {
+    const int a = q / nf, f = q % nf;
+    double s = 0;
+    for (int al = 0; al < P; ++al) {
+      const double v = C[(al * na + a) * nf + f];
+      s += v * v;
+    }
+    atomicAdd(&s_n[0][a], s);
+    atomicAdd(&s_n[1][f], s);
+  }
+  // Gram (fixed a): G[f][f'] = sum_al C[al][a][f] C[al][a][f'];  sum of squares over (f,f')
+  for (int q = tid; q < na * nf * nf; q += 256) {
+    const int a = q / (nf * nf), f = (q / nf) % nf, f2 = q % nf;
+    double s = 0;
+    for (int al = 0; al < P; ++al) s += C[(al * na + a) * nf + f] * C[(al * na + a) * nf + f2];
+    atomicAdd(&s_g[0][a], s * s);
+  }
+  // Gram (fixed f): G[a][a'] = sum_al C[al][a][f] C[al][a'][f]
+  for (int q = tid; q < nf * na * na; q += 256) {
+    const int f = q / (na * na), a = (q / na) % na, a2 = q % na;
+    double s = 0;
+    for (int al = 0; al < P; ++al) s += C[(al * na + a) * nf + f] * C[(al * na + a2) * nf + f];
+    atomicAdd(&s_g[1][f], s * s);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double nA = 0, gA = 0, nF = 0, gF = 0;
+    for (int a = 0; a < na; ++a) {
+      nA = fmax(nA, s_n[0][a]);
+      gA = fmax(gA, s_g[0][a]);
+    }
+    for (int f = 0; f < nf; ++f) {
+      nF = fmax(nF, s_n[1][f]);
+      gF = fmax(gF, s_g[1][f]);
+    }
+    out[cb].nA = sqrt(nA);
+    out[cb].gA = sqrt(sqrt(gA));
+    out[cb].nF = sqrt(nF);
+    out[cb].gF = sqrt(sqrt(gF));
+  }
+}
+
+// plan-time: CS-ERI factor Q_AF = sqrt(max_{a,f} (Aa Ff|Aa Ff)) under set semantics
+// (eq. CS-ERI); qsrc[5*cb..]: kept indices of C(F,A,-R), V(A,A), V(A,F), V(F,A), V(F,F) or -1
+__global__ __launch_bounds__(256) void k_cq(const double *__restrict__ Cbuf, const long long *__restrict__ c_off,
+                                            const int *__restrict__ c_row, const int *__restrict__ c_col,
+                                            const double *__restrict__ Vbuf, const long long *__restrict__ v_off,
+                                            const int *__restrict__ qsrc, const int *__restrict__ nao,
+                                            const int *__restrict__ nabf, int nC, CNorm *__restrict__ out) {
+  const int cb = blockIdx.x;
+  if (cb >= nC) return;
+  const int A = c_row[cb], F = c_col[cb];
+  const int PA = nabf[A], PF = nabf[F], na = nao[A], nf = nao[F];
+  const int *src = qsrc + 5 * cb;
+  const double *cAF = Cbuf + c_off[cb];
+  const double *cFA = src[0] >= 0 ? Cbuf + c_off[src[0]] : nullptr;
+  const double *vAA = src[1] >= 0 ? Vbuf + v_off[src[1]] : nullptr;
+  const double *vAF = src[2] >= 0 ? Vbuf + v_off[src[2]] : nullptr;
+  const double *vFA = src[3] >= 0 ? Vbuf + v_off[src[3]] : nullptr;
+  const double *vFF = src[4] >= 0 ? Vbuf + v_off[src[4]] : nullptr;
+  const bool onsite = src[0] == -2;  // marks F == A in the home cell
+  __shared__ double s_best[256];
+  double best = 0.0;
+  for (int q = threadIdx.x; q < na * nf; q += 256) {
+    const int a = q / nf, f = q % nf;
+    double val = 0.0;
+    if (vAA)
+      for (int al = 0; al < PA; ++al) {
+        const double ua = cAF[(al * na + a) * nf + f];
+        double s = 0;
+        for (int be = 0; be < PA; ++be) s += vAA[al * PA + be] * cAF[(be * na + a) * nf + f];
+        val += ua * s;
+      }
+    if (!onsite && cFA) {
+      if (vAF)
+        for (int al = 0; al < PA; ++al) {
+          const double ua = cAF[(al * na + a) * nf + f];
+          double s = 0;
+          for (int be = 0; be < PF; ++be) s += vAF[al * PF + be] * cFA[(be * nf + f) * na + a];
+          val += ua * s;
+        }
+      if (vFA)
+        for (int al = 0; al < PF; ++al) {
+          const double uf = cFA[(al * nf + f) * na + a];
+          double s = 0;
+          for (int be = 0; be < PA; ++be) s += vFA[al * PA + be] * cAF[(be * na + a) * nf + f];
+          val += uf * s;
+        }
+      if (vFF)
+        for (int al = 0; al < PF; ++al) {
+          const double uf = cFA[(al * nf + f) * na + a];
+          double s = 0;
+          for (int be = 0; be < PF; ++be) s += vFF[al * PF + be] * cFA[(be * nf + f) * na + a];
+          val += uf * s;
+        }
+    }
+    best = fmax(best, val);
+  }
+  s_best[threadIdx.x] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0;
+    for (int t = 0; t < 256; ++t) b = fmax(b, s_best[t]);
+    out[cb].Q = sqrt(b);
+  }
+}
+
+// plan-time: gV = sqrt(||V V^T||_F) per kept V block
+__global__ __launch_bounds__(256) void k_vnorm(const double *__restrict__ Vbuf, const long long *__restrict__ v_off,
+                                               const int *__restrict__ v_row, const int *__restrict__ v_col,
+                                               const int *__restrict__ nabf, int nV, double *__restrict__ gV) {
+  const int vb = blockIdx.x;
+  if (vb >= nV) return;
+  const int PA = nabf[v_row[vb]], PB = nabf[v_col[vb]];
+  const double *V = Vbuf + v_off[vb];
+  __shared__ double s_acc[256];
+  double acc = 0;
+  for (int q = threadIdx.x; q < PA * PA; q += 256) {
+    const int x = q / PA, y = q % PA;
+    double s = 0;
+    for (int k = 0; k < PB; ++k) s += V[x * PB + k] * V[y * PB + k];
+    acc += s * s;
+  }
+  s_acc[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_acc[threadIdx.x] += s_acc[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gV[vb] = sqrt(sqrt(s_acc[0]));
+}
+
+// per build: gather D blocks from the caller layout into the compact layout
+__global__ void k_dgather(const double *__restrict__ src, const long long *__restrict__ src_off,
+                          const long long *__restrict__ dst_off, int nD, long long base, double *__restrict__ dst) {
+  const int b = blockIdx.x;
+  if (b >= nD) return;
+  const long long n = dst_off[base + b + 1] - dst_off[base + b];
+  const double *s = src + src_off[b];
+  double *d = dst + dst_off[base + b];
+  for (long long q = threadIdx.x; q < n; q += blockDim.x) d[q] = s[q];
+}
+
+// per build: D pre-screen (max-abs > eps_D) and gD = sqrt(||D D^T||_F)
+__global__ __launch_bounds__(64) void k_dprep(const double *__restrict__ Dbuf, const long long *__restrict__ d_off,
+                                              const int *__restrict__ d_row, const int *__restrict__ d_col,
+                                              const int *__restrict__ nao, int nD, double eps_D, int pre,
+                                              double *__restrict__ gD, uint8_t *__restrict__ keepD) {
+  const int b = blockIdx.x * 4 + (threadIdx.x >> 4);
+  const int l = threadIdx.x & 15;
+  if (b >= nD) return;
+  const int nr = nao[d_row[b]], nc = nao[d_col[b]];
+  const double *D = Dbuf + d_off[b];
+  double mx = 0, acc = 0;
+  for (int q = l; q < nr * nr; q += 16) {
+    const int x = q / nr, y = q % nr;
+    double s = 0;
+    for (int k = 0; k < nc; ++k) s += D[x * nc + k] * D[y * nc + k];
+    acc += s * s;
+  }
+  for (int q = l; q < nr * nc; q += 16) mx = fmax(mx, fabs(D[q]));
+  for (int o = 8; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o, 16);
+    mx = fmax(mx, __shfl_xor(mx, o, 16));
+  }
+  if (l == 0) {
+    gD[b] = sqrt(sqrt(acc));
+    keepD[b] = pre ? (mx > eps_D) : 1;
+  }
+}
+
+__global__ void k_zero(double *__restrict__ p, long long n) {
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+    p[q] = 0.0;
+}
+
+__global__ void k_reset(unsigned int *ticket, unsigned long long *counters) {
+  if (threadIdx.x == 0) *ticket = 0;
+  if (threadIdx.x < kCntN) counters[threadIdx.x] = 0;
+}
+
+// energy: per-workgroup double-double partial sums of <D, Sigma>
+__global__ __launch_bounds__(256) void k_energy(const double *__restrict__ D, const double *__restrict__ S,
+                                                long long n, double *__restrict__ part) {
+  __shared__ double sh[256], sl[256];
+  double hi = 0, lo = 0;
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < n; q += (long long)gridDim.x * 256) {
+    const double p = D[q] * S[q];
+    const double pe = fma(D[q], S[q], -p);
+    const double t = hi + p;
+    const double bp = t - hi;
+    const double e = (hi - (t - bp)) + (p - bp);
+    hi = t;
+    lo += e + pe;
+  }
+  sh[threadIdx.x] = hi;
+  sl[threadIdx.x] = lo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double h = 0, c = 0;
+    for (int t = 0; t < 256; ++t) {
+      const double p = sh[t];
+      const double s = h + p;
+      const double bp = s - h;
+      c += (h - (s - bp)) + (p - bp) + sl[t];
+      h = s;
+    }
+    part[2 * blockIdx.x] = h;
+    part[2 * blockIdx.x + 1] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// launch wrappers (host side)
+hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles,
+                       hipStream_t s) {
+  KParams kp{rows_cap, cols_cap, acc_doubles};
+  const size_t dyn = (size_t)rows_cap + 2 * (size_t)cols_cap + (size_t)NW * acc_doubles * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_main, dim3(n_slots), dim3(NT), dyn, s, P, kp);
+  return hipGetLastError();
+}
+
+size_t main_static_lds() { return sizeof(ItemLds) + sizeof(int); }
+int main_threads() { return NT; }
+int main_maxnb() { return MAXNB; }
+int main_maxn() { return MAXN; }
+int main_nwaves() { return NW; }
+
+hipError_t launch_cnorm(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
+                        const int *nao, const int *nabf, int nC, CNorm *out, hipStream_t s) {
+  if (nC > 0) hipLaunchKernelGGL(k_cnorm, dim3(nC), dim3(256), 0, s, Cbuf, c_off, c_row, c_col, nao, nabf, nC, out);
+  return hipGetLastError();
+}
+hipError_t launch_cq(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
+                     const double *Vbuf, const long long *v_off, const int *qsrc, const int *nao, const int *nabf,
+                     int nC, CNorm *out, hipStream_t s) {
+  if (nC > 0)
+    hipLaunchKernelGGL(k_cq, dim3(nC), dim3(256), 0, s, Cbuf, c_off, c_row, c_col, Vbuf, v_off, qsrc, nao, nabf, nC,
+                       out);
+  return hipGetLastError();
+}
+hipError_t launch_vnorm(const double *Vbuf, const long long *v_off, const int *v_row, const int *v_col,
+                        const int *nabf, int nV, double *gV, hipStream_t s) {
+  if (nV > 0) hipLaunchKernelGGL(k_vnorm, dim3(nV), dim3(256), 0, s, Vbuf, v_off, v_row, v_col, nabf, nV, gV);
+  return hipGetLastError();
+}
+hipError_t launch_dgather(const double *src, const long long *src_off, const long long *dst_off, int nD,
+                          long long base, double *dst, hipStream_t s) {
+  if (nD > 0) hipLaunchKernelGGL(k_dgather, dim3(nD), dim3(64), 0, s, src, src_off, dst_off, nD, base, dst);
+  return hipGetLastError();
+}
+hipError_t launch_dprep(const double *Dbuf, const long long *d_off, const int *d_row, const int *d_col,
+                        const int *nao, int nD, double eps_D, int pre, double *gD, uint8_t *keepD, hipStream_t s) {
+  if (nD > 0)
+    hipLaunchKernelGGL(k_dprep, dim3((nD + 3) / 4), dim3(64), 0, s, Dbuf, d_off, d_row, d_col, nao, nD, eps_D, pre, gD,
+                       keepD);
+  return hipGetLastError();
+}
+hipError_t launch_zero(double *p, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ticket, counters);
+  return hipGetLastError();
+}
+hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(nblk), dim3(256), 0, s, D, S, n, part);
+  return hipGetLastError();
+}
+
+}  // namespace hfx

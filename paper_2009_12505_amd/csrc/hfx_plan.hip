@@ -1,0 +1,821 @@
+// Host side of the C ABI (include/hfx.h): validation, indexing, device
+// layouts, and the stream-ordered build.  The paper's per-geometry work
+// (Algorithm 5, "Calculate C and V": pre-screening, norms, CS-ERI factors)
+// happens in hfx_plan_create; the per-SCF-step work ("Calculate
+// exact-exchange") in hfx_build.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hfx.h"
+#include "hfx_internal.h"
+
+namespace hfx {
+hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles, hipStream_t s);
+size_t main_static_lds();
+int main_threads();
+int main_maxnb();
+int main_maxn();
+int main_nwaves();
+hipError_t launch_cnorm(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
+                        const int *nao, const int *nabf, int nC, CNorm *out, hipStream_t s);
+hipError_t launch_cq(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
+                     const double *Vbuf, const long long *v_off, const int *qsrc, const int *nao, const int *nabf,
+                     int nC, CNorm *out, hipStream_t s);
+hipError_t launch_vnorm(const double *Vbuf, const long long *v_off, const int *v_row, const int *v_col,
+                        const int *nabf, int nV, double *gV, hipStream_t s);
+hipError_t launch_dgather(const double *src, const long long *src_off, const long long *dst_off, int nD,
+                          long long base, double *dst, hipStream_t s);
+hipError_t launch_dprep(const double *Dbuf, const long long *d_off, const int *d_row, const int *d_col,
+                        const int *nao, int nD, double eps_D, int pre, double *gD, uint8_t *keepD, hipStream_t s);
+hipError_t launch_zero(double *p, long long n, hipStream_t s);
+hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, hipStream_t s);
+hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s);
+}  // namespace hfx
+
+using namespace hfx;
+
+namespace {
+
+thread_local std::string g_err;
+
+hfx_status fail(hfx_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+struct Key {
+  int32_t row, col, r;
+  bool operator==(const Key &o) const { return row == o.row && col == o.col && r == o.r; }
+};
+struct KeyHash {
+  size_t operator()(const Key &k) const {
+    uint64_t h = (uint64_t)(uint32_t)k.row * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)(uint32_t)k.col + 0x7F4A7C159E3779B9ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)(uint32_t)k.r * 0xBF58476D1CE4E5B9ull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+
+constexpr int kRMax = 200;
+
+bool r_ok(const int32_t *R) {
+  for (int k = 0; k < 3; ++k)
+    if (R[k] < -kRMax || R[k] > kRMax) return false;
+  return true;
+}
+
+}  // namespace
+
+struct hfx_plan {
+  int n_cells = 0;
+  std::vector<int> atom_off;  // n_cells + 1
+  std::vector<int> nao, nabf, cell_of, local_of;
+  std::vector<int> cell_natoms;
+  hfx_thresholds th{};
+  uint32_t stages = HFX_SCREEN_ALL;
+  int precision = HFX_PREC_FP64;
+  int scheduler = HFX_SCHED_LPT;
+  hipStream_t stream = nullptr;
+  bool poisoned = false;
+  uint64_t max_bytes = 0, used_bytes = 0;
+  std::vector<void *> allocs;
+
+  // D pattern per cell
+  std::vector<std::vector<int32_t>> d_row, d_col, d_R;
+  std::vector<std::vector<int64_t>> d_inoff;  // caller offsets
+  std::vector<std::vector<int64_t>> sig_off;  // compact offsets per cell (n+1)
+  std::vector<int64_t> dbase;                 // first global D id per cell (n_cells+1)
+  std::vector<int64_t> sbase;                 // first element in Sbuf per cell (n_cells+1)
+  std::vector<long long *> d_inoff_dev;       // per cell, device copy of caller offsets
+  std::vector<int32_t> d_row_g, d_col_g;      // global atom ids per global D id
+  int32_t *d_row_dev = nullptr, *d_col_dev = nullptr;
+  int64_t nD = 0;
+
+  // items
+  std::vector<Item> items;
+  std::vector<int32_t> order;
+  int64_t n_items = 0;
+
+  DevPlan dp{};
+  int n_slots = 0, rows_cap = 0, cols_cap = 0, acc_doubles = 0;
+  double *part = nullptr;  // energy partial sums
+  int part_blocks = 1024;
+  double *staging = nullptr;  // pinned host staging for D
+  size_t staging_n = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+
+  ~hfx_plan() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (staging) (void)hipHostFree(staging);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (ev2) (void)hipEventDestroy(ev2);
+  }
+
+  template <class T>
+  hfx_status dalloc(T **p, size_t n) {
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (max_bytes && used_bytes + bytes > max_bytes)
+      return fail(HFX_ERR_OOM, "device footprint would exceed max_device_bytes (%llu + %zu > %llu)",
+                  (unsigned long long)used_bytes, bytes, (unsigned long long)max_bytes);
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HFX_ERR_OOM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    allocs.push_back(q);
+    used_bytes += bytes;
+    *p = (T *)q;
+    return HFX_OK;
+  }
+  template <class T>
+  hfx_status upload(T **p, const std::vector<T> &v) {
+    hfx_status st = dalloc(p, v.size());
+    if (st) return st;
+    if (!v.empty() && hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+      return hip_fail("hipMemcpy");
+    return HFX_OK;
+  }
+  hfx_status hip_fail(const char *what) {
+    hipError_t e = hipGetLastError();
+    poisoned = true;
+    return fail(HFX_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
+  }
+};
+
+#define HIPCHK(plan, x)                                  \
+  do {                                                   \
+    if ((x) != hipSuccess) return (plan)->hip_fail(#x);  \
+  } while (0)
+
+namespace {
+
+double max_abs(const double *x, int64_t n) {
+  double m = 0;
+  for (int64_t i = 0; i < n; ++i) m = std::max(m, std::fabs(x[i]));
+  return m;
+}
+
+// host view of one cell's block set (data fetched to the host if it lives on the device)
+struct HostBlocks {
+  const hfx_blocks *b = nullptr;
+  const double *data = nullptr;
+  std::vector<double> copy;
+};
+
+hfx_status fetch(const hfx_blocks &b, const std::vector<int64_t> &sizes, HostBlocks &hb, const char *what) {
+  hb.b = &b;
+  if (b.n_blocks == 0) return HFX_OK;
+  if (!b.data) return fail(HFX_ERR_ARG, "%s: data is NULL", what);
+  if (!b.on_device) {
+    hb.data = b.data;
+    return HFX_OK;
+  }
+  int64_t end = 0;
+  for (int64_t k = 0; k < b.n_blocks; ++k) end = std::max(end, b.off[k] + sizes[k]);
+  hb.copy.resize((size_t)end);
+  if (hipMemcpy(hb.copy.data(), b.data, (size_t)end * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HFX_ERR_HIP, "%s: copy of device data failed", what);
+  }
+  hb.data = hb.copy.data();
+  return HFX_OK;
+}
+
+hfx_status check_blocks(const hfx_blocks &b, int n_atoms, const char *what, bool need_data) {
+  if (b.n_blocks < 0) return fail(HFX_ERR_ARG, "%s: negative n_blocks", what);
+  if (b.n_blocks > 0 && (!b.row || !b.col || !b.R || !b.off))
+    return fail(HFX_ERR_ARG, "%s: NULL index array", what);
+  if (need_data && b.n_blocks > 0 && !b.data) return fail(HFX_ERR_ARG, "%s: NULL data", what);
+  for (int64_t k = 0; k < b.n_blocks; ++k) {
+    if (b.row[k] < 0 || b.row[k] >= n_atoms || b.col[k] < 0 || b.col[k] >= n_atoms)
+      return fail(HFX_ERR_SHAPE, "%s: block %lld has atom index out of range", what, (long long)k);
+    if (b.off[k] < 0) return fail(HFX_ERR_SHAPE, "%s: block %lld has a negative offset", what, (long long)k);
+    if (!r_ok(b.R + 3 * k)) return fail(HFX_ERR_UNSUPPORTED, "%s: lattice vector beyond +-%d", what, kRMax);
+  }
+  return HFX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hfx_abi_version(void) { return HFX_ABI_VERSION; }
+const char *hfx_last_error(void) { return g_err.c_str(); }
+
+void hfx_plan_destroy(hfx_plan *plan) { delete plan; }
+
+hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blocks *C, const hfx_blocks *V,
+                           const hfx_blocks *D_pattern, const hfx_thresholds *th, const hfx_options *opt,
+                           hfx_plan **out) {
+  if (!out) return fail(HFX_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_cells < 1 || !cells || !C || !V || !D_pattern || !th)
+    return fail(HFX_ERR_ARG, "n_cells < 1 or a NULL argument");
+  const double eps[5] = {th->eps_C, th->eps_V, th->eps_D, th->eps_cs_eri, th->eps_cs_mat};
+  for (double e : eps)
+    if (!std::isfinite(e) || e < 0) return fail(HFX_ERR_ARG, "thresholds must be finite and >= 0");
+  hfx_options o{};
+  if (opt) o = *opt;
+  if (o.precision != HFX_PREC_FP64)
+    return fail(HFX_ERR_UNSUPPORTED, "precision %d is not available in this build", o.precision);
+  if (o.scheduler < HFX_SCHED_PLAN || o.scheduler > HFX_SCHED_MLP)
+    return fail(HFX_ERR_ARG, "unknown scheduler %d", o.scheduler);
+  if (o.scheduler == HFX_SCHED_MLP && !o.mlp_weights)
+    return fail(HFX_ERR_ARG, "HFX_SCHED_MLP needs mlp_weights");
+
+  auto plan = std::make_unique<hfx_plan>();
+  hfx_plan *p = plan.get();
+  p->n_cells = n_cells;
+  p->th = *th;
+  p->stages = o.stages ? o.stages : HFX_SCREEN_ALL;
+  p->precision = o.precision;
+  p->scheduler = o.scheduler;
+  p->stream = (hipStream_t)o.stream;
+  p->max_bytes = o.max_device_bytes;
+  const bool pre = p->stages & HFX_SCREEN_PRE;
+
+  // ---- atoms
+  p->atom_off.assign(n_cells + 1, 0);
+  for (int c = 0; c < n_cells; ++c) {
+    const hfx_cell &cl = cells[c];
+    if (cl.n_atoms < 1 || !cl.pos || !cl.species || cl.n_species < 1 || !cl.sp)
+      return fail(HFX_ERR_ARG, "cell %d: empty or NULL fields", c);
+    const double *L = cl.lattice;
+    const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                       L[2] * (L[3] * L[7] - L[4] * L[6]);
+    if (!std::isfinite(det) || std::fabs(det) < 1e-8) return fail(HFX_ERR_ARG, "cell %d: singular lattice", c);
+    for (int s = 0; s < cl.n_species; ++s)
+      if (cl.sp[s].n_ao < 1 || cl.sp[s].n_ao > main_maxn() || cl.sp[s].n_abf < 1 || cl.sp[s].n_abf > 512)
+        return fail(HFX_ERR_UNSUPPORTED, "cell %d species %d: n_ao must be 1..%d and n_abf 1..512", c, s,
+                    main_maxn());
+    p->atom_off[c + 1] = p->atom_off[c] + cl.n_atoms;
+    p->cell_natoms.push_back(cl.n_atoms);
+    for (int i = 0; i < cl.n_atoms; ++i) {
+      const int s = cl.species[i];
+      if (s < 0 || s >= cl.n_species) return fail(HFX_ERR_SHAPE, "cell %d atom %d: species out of range", c, i);
+      p->nao.push_back(cl.sp[s].n_ao);
+      p->nabf.push_back(cl.sp[s].n_abf);
+      p->cell_of.push_back(c);
+      p->local_of.push_back(i);
+    }
+  }
+  const int NA = p->atom_off[n_cells];
+
+  // home set
+  std::vector<uint8_t> is_home(NA, o.home_subset ? 0 : 1);
+  if (o.home_subset) {
+    if (o.n_home_subset < 0) return fail(HFX_ERR_ARG, "negative n_home_subset");
+    for (int k = 0; k < o.n_home_subset; ++k) {
+      const int a = o.home_subset[k];
+      if (a < 0 || a >= NA) return fail(HFX_ERR_ARG, "home_subset entry %d out of range", a);
+      is_home[a] = 1;
+    }
+  }
+
+  // ---- C, V: validation, pre-screening, symmetry checks
+  struct KC {
+    int cell, k;
+    double dist;
+  };
+  std::vector<std::vector<KC>> crow(NA);     // kept C blocks per global row atom
+  std::vector<std::vector<int>> vkept(n_cells);
+  std::vector<HostBlocks> hC(n_cells), hV(n_cells);
+  std::vector<std::vector<int64_t>> csz(n_cells), vsz(n_cells);
+  std::vector<std::unordered_map<Key, int, KeyHash>> vmap(n_cells), cmap(n_cells);
+  std::vector<std::vector<uint8_t>> ckeep(n_cells), vkeep(n_cells);
+  for (int c = 0; c < n_cells; ++c) {
+    const hfx_cell &cl = cells[c];
+    const int n = cl.n_atoms, a0 = p->atom_off[c];
+    hfx_status st;
+    if ((st = check_blocks(C[c], n, "C", true)) || (st = check_blocks(V[c], n, "V", true)) ||
+        (st = check_blocks(D_pattern[c], n, "D_pattern", false)))
+      return st;
+    csz[c].resize(C[c].n_blocks);
+    for (int64_t k = 0; k < C[c].n_blocks; ++k)
+      csz[c][k] = (int64_t)p->nabf[a0 + C[c].row[k]] * p->nao[a0 + C[c].row[k]] * p->nao[a0 + C[c].col[k]];
+    vsz[c].resize(V[c].n_blocks);
+    for (int64_t k = 0; k < V[c].n_blocks; ++k)
+      vsz[c][k] = (int64_t)p->nabf[a0 + V[c].row[k]] * p->nabf[a0 + V[c].col[k]];
+    if ((st = fetch(C[c], csz[c], hC[c], "C")) || (st = fetch(V[c], vsz[c], hV[c], "V"))) return st;
+    const double *cd = hC[c].data, *vd = hV[c].data;
+    ckeep[c].assign(C[c].n_blocks, 0);
+    for (int64_t k = 0; k < C[c].n_blocks; ++k) {
+      const int32_t *R = C[c].R + 3 * k;
+      Key key{C[c].row[k], C[c].col[k], pack_r(R[0], R[1], R[2])};
+      if (!cmap[c].emplace(key, (int)k).second) return fail(HFX_ERR_SHAPE, "C: duplicate block %lld", (long long)k);
+      const double *blk = cd + C[c].off[k];
+      const double m = max_abs(blk, csz[c][k]);
+      ckeep[c][k] = pre ? (m > th->eps_C) : 1;
+      if (C[c].row[k] == C[c].col[k] && R[0] == 0 && R[1] == 0 && R[2] == 0) {
+        const int P = p->nabf[a0 + C[c].row[k]], na = p->nao[a0 + C[c].row[k]];
+        for (int al = 0; al < P; ++al)
+          for (int a = 0; a < na; ++a)
+            for (int f = a + 1; f < na; ++f)
+              if (std::fabs(blk[(al * na + a) * na + f] - blk[(al * na + f) * na + a]) > 1e-12 * m)
+                return fail(HFX_ERR_SYMMETRY, "C: on-site block of atom %d is not symmetric in its AO indices",
+                            C[c].row[k]);
+      }
+    }
+    vkeep[c].assign(V[c].n_blocks, 0);
+    for (int64_t k = 0; k < V[c].n_blocks; ++k) {
+      const int32_t *R = V[c].R + 3 * k;
+      Key key{V[c].row[k], V[c].col[k], pack_r(R[0], R[1], R[2])};
+      if (!vmap[c].emplace(key, (int)k).second) return fail(HFX_ERR_SHAPE, "V: duplicate block %lld", (long long)k);
+      vkeep[c][k] = pre ? (max_abs(vd + V[c].off[k], vsz[c][k]) > th->eps_V) : 1;
+    }
+    for (int64_t k = 0; k < V[c].n_blocks; ++k) {
+      const int32_t *R = V[c].R + 3 * k;
+      auto it = vmap[c].find(Key{V[c].col[k], V[c].row[k], pack_r(-R[0], -R[1], -R[2])});
+      if (it == vmap[c].end())
+        return fail(HFX_ERR_SYMMETRY, "V: block (%d,%d,R) has no partner (col,row,-R)", V[c].row[k], V[c].col[k]);
+      if (it->second < k) continue;
+      const int PA = p->nabf[a0 + V[c].row[k]], PB = p->nabf[a0 + V[c].col[k]];
+      const double *x = vd + V[c].off[k], *y = vd + V[c].off[it->second];
+      const double m = std::max(max_abs(x, vsz[c][k]), 1e-300);
+      for (int a = 0; a < PA; ++a)
+        for (int b = 0; b < PB; ++b)
+          if (std::fabs(x[a * PB + b] - y[b * PA + a]) > 1e-10 * m)
+            return fail(HFX_ERR_SYMMETRY, "V(%d,%d,R) != V(%d,%d,-R)^T", V[c].row[k], V[c].col[k], V[c].col[k],
+                        V[c].row[k]);
+    }
+    // kept C per row atom with the pair distance
+    const double *L = cl.lattice;
+    for (int64_t k = 0; k < C[c].n_blocks; ++k) {
+      if (!ckeep[c][k]) continue;
+      const int r = C[c].row[k], q = C[c].col[k];
+      const int32_t *R = C[c].R + 3 * k;
+      double d[3];
+      for (int x = 0; x < 3; ++x)
+        d[x] = cl.pos[3 * q + x] - cl.pos[3 * r + x] + R[0] * L[x] + R[1] * L[3 + x] + R[2] * L[6 + x];
+      crow[a0 + r].push_back(KC{c, (int)k, std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])});
+    }
+    for (int64_t k = 0; k < V[c].n_blocks; ++k)
+      if (vkeep[c][k]) vkept[c].push_back((int)k);
+  }
+
+  // ---- kept C in (row atom, distance) order
+  std::vector<int32_t> c_start(NA + 1, 0), c_row, c_col, c_Rp;
+  std::vector<long long> c_off;
+  int64_t cdoubles = 0;
+  int max_nbr = 0;
+  std::vector<std::unordered_map<int, int>> cnew(n_cells);  // (cell, caller index) -> kept index
+  for (int a = 0; a < NA; ++a) {
+    auto &lst = crow[a];
+    std::stable_sort(lst.begin(), lst.end(), [](const KC &x, const KC &y) { return x.dist < y.dist; });
+    max_nbr = std::max(max_nbr, (int)lst.size());
+    for (const KC &kc : lst) {
+      const int c = kc.cell, k = kc.k, a0 = p->atom_off[c];
+      cnew[c][k] = (int)c_row.size();
+      c_row.push_back(a0 + C[c].row[k]);
+      c_col.push_back(a0 + C[c].col[k]);
+      const int32_t *R = C[c].R + 3 * k;
+      c_Rp.push_back(pack_r(R[0], R[1], R[2]));
+      c_off.push_back(cdoubles);
+      cdoubles += (csz[c][k] + 31) / 32 * 32;
+    }
+    c_start[a + 1] = (int)c_row.size();
+  }
+  if (max_nbr > main_maxnb())
+    return fail(HFX_ERR_UNSUPPORTED, "an atom has %d kept C blocks (limit %d)", max_nbr, main_maxnb());
+  const int nC = (int)c_row.size();
+  std::vector<double> cstage((size_t)cdoubles, 0.0);
+  {
+    int kk = 0;
+    for (int a = 0; a < NA; ++a)
+      for (const KC &kc : crow[a]) {
+        std::memcpy(cstage.data() + c_off[kk], hC[kc.cell].data + C[kc.cell].off[kc.k],
+                    csz[kc.cell][kc.k] * sizeof(double));
+        ++kk;
+      }
+  }
+
+  // ---- kept V
+  std::vector<int32_t> v_row, v_col, v_Rp;
+  std::vector<long long> v_off;
+  std::vector<std::unordered_map<int, int>> vnew(n_cells);
+  int64_t vdoubles = 0;
+  for (int c = 0; c < n_cells; ++c) {
+    const int a0 = p->atom_off[c];
+    for (int k : vkept[c]) {
+      vnew[c][k] = (int)v_row.size();
+      v_row.push_back(a0 + V[c].row[k]);
+      v_col.push_back(a0 + V[c].col[k]);
+      const int32_t *R = V[c].R + 3 * k;
+      v_Rp.push_back(pack_r(R[0], R[1], R[2]));
+      v_off.push_back(vdoubles);
+      vdoubles += (vsz[c][k] + 31) / 32 * 32;
+    }
+  }
+  const int nV = (int)v_row.size();
+  std::vector<double> vstage((size_t)vdoubles, 0.0);
+  for (int c = 0, kk = 0; c < n_cells; ++c)
+    for (int k : vkept[c]) {
+      std::memcpy(vstage.data() + v_off[kk], hV[c].data + V[c].off[k], vsz[c][k] * sizeof(double));
+      ++kk;
+    }
+
+  // ---- CS-ERI sources per kept C block: C(F,A,-R), V(A,A,0), V(A,F,R), V(F,A,-R), V(F,F,0)
+  std::vector<int32_t> qsrc((size_t)nC * 5, -1);
+  {
+    int kk = 0;
+    for (int a = 0; a < NA; ++a)
+      for (const KC &kc : crow[a]) {
+        const int c = kc.cell, k = kc.k;
+        const int A = C[c].row[k], F = C[c].col[k];
+        const int32_t *R = C[c].R + 3 * k;
+        const int32_t Rp = pack_r(R[0], R[1], R[2]), Rm = pack_r(-R[0], -R[1], -R[2]), R0 = pack_r(0, 0, 0);
+        auto vfind = [&](int x, int y, int32_t rr) {
+          auto it = vmap[c].find(Key{x, y, rr});
+          if (it == vmap[c].end() || !vkeep[c][it->second]) return -1;
+          return vnew[c][it->second];
+        };
+        int32_t *q = &qsrc[(size_t)kk * 5];
+        if (A == F && Rp == R0) {
+          q[0] = -2;
+        } else {
+          auto it = cmap[c].find(Key{F, A, Rm});
+          q[0] = (it != cmap[c].end() && ckeep[c][it->second]) ? cnew[c][it->second] : -1;
+          q[2] = vfind(A, F, Rp);
+          q[3] = vfind(F, A, Rm);
+          q[4] = vfind(F, F, R0);
+        }
+        q[1] = vfind(A, A, R0);
+        ++kk;
+      }
+  }
+
+  // ---- items: kept V blocks (A,B,R) with A a home atom; LPT cost = |N(A)| |N(B)|
+  std::vector<double> cost;
+  for (int vb = 0; vb < nV; ++vb) {
+    const int A = v_row[vb], B = v_col[vb];
+    if (!is_home[A]) continue;
+    const int nF = c_start[A + 1] - c_start[A], nG = c_start[B + 1] - c_start[B];
+    if (nF == 0 || nG == 0) continue;
+    p->items.push_back(Item{A, B, v_Rp[vb], vb});
+    cost.push_back((double)nF * nG);
+  }
+  p->n_items = (int64_t)p->items.size();
+  p->order.resize(p->n_items);
+  std::iota(p->order.begin(), p->order.end(), 0);
+  if (p->scheduler == HFX_SCHED_LPT)
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+
+  // ---- D pattern: compact offsets, sorted lookup, pair tables
+  p->d_row.resize(n_cells);
+  p->d_col.resize(n_cells);
+  p->d_R.resize(n_cells);
+  p->d_inoff.resize(n_cells);
+  p->sig_off.resize(n_cells);
+  p->dbase.assign(n_cells + 1, 0);
+  p->sbase.assign(n_cells + 1, 0);
+  std::vector<long long> d_off_g;
+  std::vector<int32_t> ptab_off(n_cells + 1, 0), pstart, pcount, dsort_R, dsort_id;
+  for (int c = 0; c < n_cells; ++c) {
+    const hfx_blocks &Dp = D_pattern[c];
+    const int n = cells[c].n_atoms, a0 = p->atom_off[c];
+    const int64_t nb = Dp.n_blocks;
+    p->d_row[c].assign(Dp.row, Dp.row + nb);
+    p->d_col[c].assign(Dp.col, Dp.col + nb);
+    p->d_R[c].assign(Dp.R, Dp.R + 3 * nb);
+    p->d_inoff[c].assign(Dp.off, Dp.off + nb);
+    p->sig_off[c].assign(nb + 1, 0);
+    for (int64_t k = 0; k < nb; ++k)
+      p->sig_off[c][k + 1] = p->sig_off[c][k] + (int64_t)p->nao[a0 + Dp.row[k]] * p->nao[a0 + Dp.col[k]];
+    p->dbase[c + 1] = p->dbase[c] + nb;
+    p->sbase[c + 1] = p->sbase[c] + p->sig_off[c][nb];
+    for (int64_t k = 0; k < nb; ++k) {
+      d_off_g.push_back(p->sbase[c] + p->sig_off[c][k]);
+      p->d_row_g.push_back(a0 + Dp.row[k]);
+      p->d_col_g.push_back(a0 + Dp.col[k]);
+    }
+    std::vector<int64_t> idx(nb);
+    std::iota(idx.begin(), idx.end(), 0);
+    auto rp = [&](int64_t k) { return pack_r(Dp.R[3 * k], Dp.R[3 * k + 1], Dp.R[3 * k + 2]); };
+    std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+      if (Dp.row[x] != Dp.row[y]) return Dp.row[x] < Dp.row[y];
+      if (Dp.col[x] != Dp.col[y]) return Dp.col[x] < Dp.col[y];
+      return rp(x) < rp(y);
+    });
+    ptab_off[c] = (int32_t)pstart.size();
+    const size_t t0 = pstart.size();
+    pstart.resize(t0 + (size_t)n * n, 0);
+    pcount.resize(t0 + (size_t)n * n, 0);
+    const int32_t sbase0 = (int32_t)dsort_R.size();
+    for (int64_t q = 0; q < nb; ++q) {
+      const int64_t k = idx[q];
+      if (q > 0 && Dp.row[idx[q - 1]] == Dp.row[k] && Dp.col[idx[q - 1]] == Dp.col[k] && rp(idx[q - 1]) == rp(k))
+        return fail(HFX_ERR_SHAPE, "D_pattern: duplicate block (%d,%d,R)", Dp.row[k], Dp.col[k]);
+      const size_t t = t0 + (size_t)Dp.row[k] * n + Dp.col[k];
+      if (pcount[t] == 0) pstart[t] = sbase0 + (int32_t)q;
+      pcount[t]++;
+      dsort_R.push_back(rp(k));
+      dsort_id.push_back((int32_t)(p->dbase[c] + k));
+    }
+  }
+  p->nD = p->dbase[n_cells];
+  d_off_g.push_back(p->sbase[n_cells]);
+  if (p->nD > (1ll << 30)) return fail(HFX_ERR_UNSUPPORTED, "too many D blocks");
+
+  // ---- per-slot scratch and LDS sizing
+  int max_n = 0, max_p = 0, min_n = 1 << 30;
+  for (int a = 0; a < NA; ++a) {
+    max_n = std::max(max_n, p->nao[a]);
+    max_p = std::max(max_p, p->nabf[a]);
+    min_n = std::min(min_n, p->nao[a]);
+  }
+  int64_t gside_max = 0;
+  for (int b = 0; b < NA; ++b) {
+    int64_t s = 0, rows = 0, cols = 0;
+    const int nb = p->nao[b];
+    for (int q = c_start[b]; q < c_start[b + 1]; ++q) {
+      const int64_t ng = p->nao[c_col[q]];
+      s += (int64_t)max_p * nb * ng + (int64_t)max_p * max_n * ng + (int64_t)max_p * max_n * nb + nb * ng * ng +
+           ng * nb * nb;
+      rows += ng;
+      cols += ng + nb;
+    }
+    gside_max = std::max(gside_max, s);
+    p->rows_cap = std::max<int>(p->rows_cap, (int)rows);
+    p->cols_cap = std::max<int>(p->cols_cap, (int)cols);
+  }
+  p->rows_cap = (p->rows_cap + 15) / 16 * 16 + 16;
+  p->cols_cap = (p->cols_cap + 15) / 16 * 16 + 16;
+  if (p->rows_cap > 255 * 64 || p->cols_cap > 32767)
+    return fail(HFX_ERR_UNSUPPORTED, "neighbour lists too long for the decode tables");
+  const int64_t nfg = (int64_t)max_nbr * max_nbr;
+  const int64_t slot = (nfg + 1) / 2 + (nfg + 7) / 8 + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
+  const int J = 16 / (2 * min_n) + 2;
+  p->acc_doubles = std::max(16 * main_maxn(), J * max_n * main_maxn());
+  const size_t lds = main_static_lds() + (size_t)p->rows_cap + 2 * (size_t)p->cols_cap +
+                     (size_t)main_nwaves() * p->acc_doubles * sizeof(double);
+  if (lds > 160 * 1024)
+    return fail(HFX_ERR_UNSUPPORTED, "workgroup would need %zu bytes of LDS (limit 163840)", lds);
+
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) n_cu = prop.multiProcessorCount;
+  }
+  (void)hipGetLastError();
+  p->n_slots = o.n_slots > 0 ? o.n_slots : n_cu;
+  if (p->n_items > 0) p->n_slots = (int)std::min<int64_t>(p->n_slots, p->n_items);
+  p->n_slots = std::max(p->n_slots, 1);
+
+  // ---- device memory
+  DevPlan &P = p->dp;
+  hfx_status st;
+  int32_t *d_nao, *d_nabf, *d_cellof, *d_localof, *d_cstart, *d_ccol, *d_cR, *d_crow, *d_vrow, *d_vcol, *d_qsrc;
+  long long *d_coff, *d_voff, *d_doff;
+  double *d_C, *d_V, *d_gV, *d_gD, *d_D, *d_S, *d_scr;
+  CNorm *d_cn;
+  int32_t *d_ptoff, *d_pstart, *d_pcount, *d_dsR, *d_dsid, *d_cellnat, *d_order, *d_drow, *d_dcol;
+  uint8_t *d_keepD;
+  Item *d_items;
+  unsigned int *d_ticket;
+  unsigned long long *d_cnt;
+  long long *d_icyc;
+  int *d_iunits;
+  std::vector<int32_t> ord32(p->order.begin(), p->order.end());
+  if ((st = p->upload(&d_nao, p->nao)) || (st = p->upload(&d_nabf, p->nabf)) ||
+      (st = p->upload(&d_cellof, p->cell_of)) || (st = p->upload(&d_localof, p->local_of)) ||
+      (st = p->upload(&d_cstart, c_start)) || (st = p->upload(&d_ccol, c_col)) || (st = p->upload(&d_crow, c_row)) ||
+      (st = p->upload(&d_cR, c_Rp)) || (st = p->upload(&d_coff, c_off)) || (st = p->upload(&d_C, cstage)) ||
+      (st = p->upload(&d_vrow, v_row)) || (st = p->upload(&d_vcol, v_col)) || (st = p->upload(&d_voff, v_off)) ||
+      (st = p->upload(&d_V, vstage)) || (st = p->upload(&d_qsrc, qsrc)) || (st = p->dalloc(&d_cn, nC)) ||
+      (st = p->dalloc(&d_gV, nV)) || (st = p->upload(&d_ptoff, ptab_off)) || (st = p->upload(&d_pstart, pstart)) ||
+      (st = p->upload(&d_pcount, pcount)) || (st = p->upload(&d_dsR, dsort_R)) ||
+      (st = p->upload(&d_dsid, dsort_id)) || (st = p->upload(&d_cellnat, p->cell_natoms)) ||
+      (st = p->upload(&d_doff, d_off_g)) || (st = p->upload(&d_drow, p->d_row_g)) ||
+      (st = p->upload(&d_dcol, p->d_col_g)) || (st = p->dalloc(&d_D, (size_t)p->sbase[n_cells])) ||
+      (st = p->dalloc(&d_S, (size_t)p->sbase[n_cells])) || (st = p->dalloc(&d_gD, (size_t)p->nD)) ||
+      (st = p->dalloc(&d_keepD, (size_t)p->nD)) || (st = p->upload(&d_items, p->items)) ||
+      (st = p->upload(&d_order, ord32)) || (st = p->dalloc(&d_ticket, 1)) || (st = p->dalloc(&d_cnt, kCntN)) ||
+      (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * 4)) ||
+      (st = p->dalloc(&d_scr, (size_t)p->n_slots * slot)) || (st = p->dalloc(&p->part, 2 * p->part_blocks)))
+    return st;
+  cstage.clear();
+  cstage.shrink_to_fit();
+  vstage.clear();
+  vstage.shrink_to_fit();
+  p->d_row_dev = d_drow;
+  p->d_col_dev = d_dcol;
+  p->d_inoff_dev.resize(n_cells);
+  for (int c = 0; c < n_cells; ++c) {
+    std::vector<long long> tmp(p->d_inoff[c].begin(), p->d_inoff[c].end());
+    if ((st = p->upload(&p->d_inoff_dev[c], tmp))) return st;
+  }
+  // zero-initialise D so that pattern blocks never hold garbage
+  HIPCHK(p, launch_zero(d_D, p->sbase[n_cells], p->stream));
+
+  P.n_atoms = NA;
+  P.nao = d_nao;
+  P.nabf = d_nabf;
+  P.cell_of = d_cellof;
+  P.local_of = d_localof;
+  P.Cbuf = d_C;
+  P.c_off = d_coff;
+  P.c_col = d_ccol;
+  P.c_R = d_cR;
+  P.c_norm = d_cn;
+  P.c_start = d_cstart;
+  P.Vbuf = d_V;
+  P.v_off = d_voff;
+  P.gV = d_gV;
+  P.ptab_off = d_ptoff;
+  P.pstart = d_pstart;
+  P.pcount = d_pcount;
+  P.dsort_R = d_dsR;
+  P.dsort_id = d_dsid;
+  P.cell_natoms = d_cellnat;
+  P.d_off = d_doff;
+  P.Dbuf = d_D;
+  P.gD = d_gD;
+  P.keepD = d_keepD;
+  P.Sbuf = d_S;
+  P.items = d_items;
+  P.order = d_order;
+  P.n_items = (int32_t)p->n_items;
+  P.eps_eri = th->eps_cs_eri;
+  P.eps_mat = th->eps_cs_mat;
+  P.stages = p->stages;
+  P.scratch = d_scr;
+  P.slot_doubles = slot;
+  P.max_nbr = max_nbr;
+  P.max_p = max_p;
+  P.max_n = max_n;
+  P.ticket = d_ticket;
+  P.counters = d_cnt;
+  P.item_cycles = d_icyc;
+  P.item_units = d_iunits;
+
+  // ---- plan-time kernels: C norms, CS-ERI factors, V norms
+  HIPCHK(p, launch_cnorm(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_cn, p->stream));
+  HIPCHK(p, launch_cq(d_C, d_coff, d_crow, d_ccol, d_V, d_voff, d_qsrc, d_nao, d_nabf, nC, d_cn, p->stream));
+  HIPCHK(p, launch_vnorm(d_V, d_voff, d_vrow, d_vcol, d_nabf, nV, d_gV, p->stream));
+  HIPCHK(p, hipEventCreate(&p->ev0));
+  HIPCHK(p, hipEventCreate(&p->ev1));
+  HIPCHK(p, hipEventCreate(&p->ev2));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  *out = plan.release();
+  return HFX_OK;
+}
+
+hfx_status hfx_sigma_layout(const hfx_plan *p, int32_t cell, hfx_blocks *layout, int64_t *n_elements) {
+  if (!p || !layout) return fail(HFX_ERR_ARG, "NULL argument");
+  if (cell < 0 || cell >= p->n_cells) return fail(HFX_ERR_ARG, "cell %d out of range", cell);
+  layout->n_blocks = (int64_t)p->d_row[cell].size();
+  layout->row = p->d_row[cell].data();
+  layout->col = p->d_col[cell].data();
+  layout->R = p->d_R[cell].data();
+  layout->off = p->sig_off[cell].data();
+  layout->data = nullptr;
+  layout->on_device = 1;
+  if (n_elements) *n_elements = p->sig_off[cell].back();
+  return HFX_OK;
+}
+
+static hfx_status stage_d(hfx_plan *p, const hfx_blocks *D) {
+  if (!D) return fail(HFX_ERR_ARG, "D is NULL");
+  for (int c = 0; c < p->n_cells; ++c) {
+    const hfx_blocks &d = D[c];
+    const int64_t nb = (int64_t)p->d_row[c].size();
+    if (d.n_blocks != nb) return fail(HFX_ERR_STATE, "cell %d: D has %lld blocks, the plan's pattern %lld", c,
+                                      (long long)d.n_blocks, (long long)nb);
+    if (nb > 0 && !d.data) return fail(HFX_ERR_ARG, "cell %d: D data is NULL", c);
+    if (d.off && std::memcmp(d.off, p->d_inoff[c].data(), nb * sizeof(int64_t)) != 0)
+      return fail(HFX_ERR_STATE, "cell %d: D offsets differ from the plan's pattern", c);
+    if (d.row && (std::memcmp(d.row, p->d_row[c].data(), nb * sizeof(int32_t)) != 0 ||
+                  std::memcmp(d.col, p->d_col[c].data(), nb * sizeof(int32_t)) != 0 ||
+                  std::memcmp(d.R, p->d_R[c].data(), 3 * nb * sizeof(int32_t)) != 0))
+      return fail(HFX_ERR_STATE, "cell %d: D block structure differs from the plan's pattern", c);
+    if (nb == 0) continue;
+    if (d.on_device) {
+      HIPCHK(p, launch_dgather(d.data, p->d_inoff_dev[c], p->dp.d_off, (int)nb, p->dbase[c],
+                               const_cast<double *>(p->dp.Dbuf), p->stream));
+    } else {
+      const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
+      if (p->staging_n < n) {
+        if (p->staging) HIPCHK(p, hipHostFree(p->staging));
+        p->staging = nullptr;
+        HIPCHK(p, hipHostMalloc((void **)&p->staging, n * sizeof(double)));
+        p->staging_n = n;
+      }
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+      for (int64_t k = 0; k < nb; ++k)
+        std::memcpy(p->staging + p->sig_off[c][k], d.data + p->d_inoff[c][k],
+                    (p->sig_off[c][k + 1] - p->sig_off[c][k]) * sizeof(double));
+      HIPCHK(p, hipMemcpyAsync(const_cast<double *>(p->dp.Dbuf) + p->sbase[c], p->staging, n * sizeof(double),
+                               hipMemcpyHostToDevice, p->stream));
+      HIPCHK(p, hipStreamSynchronize(p->stream));
+    }
+  }
+  return HFX_OK;
+}
+
+hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx_build_stats *stats) {
+  if (!p) return fail(HFX_ERR_ARG, "plan is NULL");
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  if (!sigma) return fail(HFX_ERR_ARG, "sigma is NULL");
+  for (int c = 0; c < p->n_cells; ++c)
+    if (!sigma[c] && p->sbase[c + 1] > p->sbase[c]) return fail(HFX_ERR_ARG, "sigma[%d] is NULL", c);
+  hfx_status st = stage_d(p, D);
+  if (st) return st;
+  DevPlan &P = p->dp;
+  const long long ntot = p->sbase[p->n_cells];
+  HIPCHK(p, hipEventRecord(p->ev0, p->stream));
+  HIPCHK(p, launch_dprep(P.Dbuf, P.d_off, p->d_row_dev, p->d_col_dev, P.nao, (int)p->nD, p->th.eps_D,
+                         (p->stages & HFX_SCREEN_PRE) ? 1 : 0, const_cast<double *>(P.gD),
+                         const_cast<uint8_t *>(P.keepD), p->stream));
+  HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
+  HIPCHK(p, launch_reset(P.ticket, P.counters, p->stream));
+  HIPCHK(p, hipEventRecord(p->ev1, p->stream));
+  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->acc_doubles, p->stream));
+  HIPCHK(p, hipEventRecord(p->ev2, p->stream));
+  for (int c = 0; c < p->n_cells; ++c) {
+    const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
+    if (n) HIPCHK(p, hipMemcpyAsync(sigma[c], P.Sbuf + p->sbase[c], n * sizeof(double), hipMemcpyDeviceToDevice,
+                                    p->stream));
+  }
+  if (stats) {
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    unsigned long long cnt[kCntN];
+    HIPCHK(p, hipMemcpy(cnt, P.counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    std::memset(stats, 0, sizeof(*stats));
+    stats->candidates = (int64_t)cnt[kCntCandidates];
+    stats->kept_cs_eri = (int64_t)cnt[kCntCsEri];
+    for (int s = 0; s < 3; ++s)
+      for (int t = 0; t < 4; ++t) stats->kept[s][t] = (int64_t)cnt[kCntKept + 4 * s + t];
+    stats->items = p->n_items;
+    stats->g_alive = (int64_t)cnt[kCntG];
+    const double mf = 2048.0 * (double)(cnt[kCntMfmaR] + cnt[kCntMfmaL] + cnt[kCntMfmaY]);
+    stats->flops_tier[0] = mf;
+    stats->flops_contract = mf;
+    float ms0 = 0, ms1 = 0;
+    HIPCHK(p, hipEventElapsedTime(&ms0, p->ev0, p->ev2));
+    HIPCHK(p, hipEventElapsedTime(&ms1, p->ev1, p->ev2));
+    stats->ms_total = ms0;
+    stats->ms_main = ms1;
+  }
+  return HFX_OK;
+}
+
+hfx_status hfx_energy(hfx_plan *p, const hfx_blocks *D, double *const *sigma, double *e_x) {
+  if (!p || !sigma || !e_x) return fail(HFX_ERR_ARG, "NULL argument");
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  hfx_status st = stage_d(p, D);
+  if (st) return st;
+  std::vector<double> part(2 * p->part_blocks);
+  for (int c = 0; c < p->n_cells; ++c) {
+    const long long n = p->sbase[c + 1] - p->sbase[c];
+    e_x[c] = 0.0;
+    if (!n) continue;
+    HIPCHK(p, launch_energy(p->dp.Dbuf + p->sbase[c], sigma[c], n, p->part, p->part_blocks, p->stream));
+    HIPCHK(p, hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    // Neumaier summation of the double-double partials
+    double s = 0, comp = 0;
+    for (double v : part) {
+      const double t = s + v;
+      comp += std::fabs(s) >= std::fabs(v) ? (s - t) + v : (v - t) + s;
+      s = t;
+    }
+    e_x[c] = 0.5 * (s + comp);
+  }
+  return HFX_OK;
+}
+
+hfx_status hfx_item_profile(hfx_plan *p, int64_t *n_items, int64_t *cycles, int64_t *units) {
+  if (!p || !n_items) return fail(HFX_ERR_ARG, "NULL argument");
+  *n_items = p->n_items;
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  if (cycles && p->n_items) {
+    std::vector<long long> c(p->n_items);
+    HIPCHK(p, hipMemcpy(c.data(), p->dp.item_cycles, c.size() * sizeof(long long), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < p->n_items; ++i) cycles[i] = c[i];
+  }
+  if (units && p->n_items) {
+    std::vector<int> u(4 * p->n_items);
+    HIPCHK(p, hipMemcpy(u.data(), p->dp.item_units, u.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < u.size(); ++i) units[i] = u[i];
+  }
+  return HFX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+"""Plan object over the C ABI (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi as A
+
+
+def _arr(x, dt):
+    return np.ascontiguousarray(x, dtype=dt)
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+class _BlockArgs:
+    """Keeps the arrays of one hfx_blocks alive while the library reads them."""
+
+    def __init__(self, b, data=None, on_device=False):
+        self.row = _arr(b.row, np.int32)
+        self.col = _arr(b.col, np.int32)
+        self.R = _arr(b.R, np.int32).reshape(-1)
+        self.off = _arr(b.off, np.int64)
+        self.data_keep = None
+        if data is None:
+            data = b.data
+        if on_device:
+            self.data_ptr = int(data.data_ptr())
+            self.data_keep = data
+        elif data is None:
+            self.data_ptr = None
+        else:
+            self.data_keep = _arr(data, np.float64)
+            self.data_ptr = self.data_keep.ctypes.data
+        self.s = A.Blocks(int(self.row.shape[0]), self.row.ctypes.data, self.col.ctypes.data, self.R.ctypes.data,
+                          self.off.ctypes.data, self.data_ptr, 1 if on_device else 0)
+
+
+class Plan:
+    """Per-geometry plan (Algorithm 5, "Calculate C and V") for one or more cells.
+
+    cells: objects with ``lattice`` (3,3), ``pos`` (n,3), ``species`` (n,), ``species_table`` [(n_ao, n_abf)]
+    C, V, D_pattern: per-cell block sets with ``row``, ``col``, ``R``, ``off``, ``data`` (host numpy)
+    thresholds: dict with eps_C, eps_V, eps_D, eps_cs_eri, eps_cs_mat
+    """
+
+    def __init__(self, cells, C, V, D_pattern, thresholds, precision=A.PREC_FP64, stages=A.SCREEN_ALL,
+                 scheduler=A.SCHED_LPT, home_subset=None, stream=None, n_slots=0, max_device_bytes=0,
+                 tier_tau=0.0, tier_tau_bf=0.0, mlp_weights=None):
+        import torch
+        self._torch = torch
+        L = A.lib()
+        self.n_cells = len(cells)
+        self._keep = []
+        ccells = (A.Cell * self.n_cells)()
+        for i, cl in enumerate(cells):
+            pos = _arr(cl.pos, np.float64).reshape(-1)
+            sp = _arr(cl.species, np.int32)
+            tab = (A.Species * len(cl.species_table))(*[A.Species(int(a), int(b)) for a, b in cl.species_table])
+            self._keep += [pos, sp, tab]
+            ccells[i].n_atoms = int(sp.shape[0])
+            for k, v in enumerate(np.asarray(cl.lattice, np.float64).reshape(-1)):
+                ccells[i].lattice[k] = float(v)
+            ccells[i].pos = pos.ctypes.data
+            ccells[i].species = sp.ctypes.data
+            ccells[i].n_species = len(cl.species_table)
+            ccells[i].sp = tab
+        cargs = [_BlockArgs(b) for b in C]
+        vargs = [_BlockArgs(b) for b in V]
+        dargs = [_BlockArgs(b, data=np.zeros(0)) for b in D_pattern]
+        cC = (A.Blocks * self.n_cells)(*[a.s for a in cargs])
+        cV = (A.Blocks * self.n_cells)(*[a.s for a in vargs])
+        cD = (A.Blocks * self.n_cells)(*[a.s for a in dargs])
+        th = A.Thresholds(thresholds["eps_C"], thresholds["eps_V"], thresholds["eps_D"], thresholds["eps_cs_eri"],
+                          thresholds["eps_cs_mat"])
+        hs = None if home_subset is None else _arr(home_subset, np.int32)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        opt = A.Options(precision, stages, tier_tau, tier_tau_bf, scheduler,
+                        None if mlp_weights is None else str(mlp_weights).encode(),
+                        ctypes.c_void_p(stream.cuda_stream), None if hs is None else hs.ctypes.data,
+                        0 if hs is None else int(hs.shape[0]), int(max_device_bytes), int(n_slots))
+        h = ctypes.c_void_p()
+        A.check(L.hfx_plan_create(self.n_cells, ctypes.byref(ccells), ctypes.byref(cC), ctypes.byref(cV),
+                                  ctypes.byref(cD), ctypes.byref(th), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.layouts = []
+        self.sizes = []
+        for c in range(self.n_cells):
+            lay = A.Blocks()
+            n = ctypes.c_int64()
+            A.check(L.hfx_sigma_layout(h, c, ctypes.byref(lay), ctypes.byref(n)))
+            nb = lay.n_blocks
+            off = np.ctypeslib.as_array(ctypes.cast(lay.off, ctypes.POINTER(ctypes.c_int64)), shape=(nb + 1,)).copy()
+            self.layouts.append(off)
+            self.sizes.append(int(n.value))
+        self.last_stats = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                A.lib().hfx_plan_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self._h = None
+
+    # ------------------------------------------------------------------ D marshalling
+    def _d_struct(self, D):
+        """D: per-cell block sets; data may be numpy (host) or a CUDA tensor (device)."""
+        args = []
+        for b in D:
+            dev = hasattr(b.data, "data_ptr")
+            args.append(_BlockArgs(b, on_device=dev))
+        return args, (A.Blocks * self.n_cells)(*[a.s for a in args])
+
+    def alloc_sigma(self):
+        torch = self._torch
+        return [torch.empty(n, dtype=torch.float64, device="cuda") for n in self.sizes]
+
+    def build(self, D, sigma=None, stats=False):
+        """Sigma^X on the D pattern of every cell (device float64 tensors, compact layout)."""
+        args, cD = self._d_struct(D)
+        if sigma is None:
+            sigma = self.alloc_sigma()
+        ptrs = (ctypes.c_void_p * self.n_cells)(*[s.data_ptr() for s in sigma])
+        st = A.BuildStats() if stats else None
+        A.check(A.lib().hfx_build(self._h, ctypes.byref(cD), ptrs, None if st is None else ctypes.byref(st)))
+        self._last_args = args  # keep host/device inputs alive until the stream passes the build
+        if st is not None:
+            self.last_stats = st.as_dict()
+        return sigma
+
+    def energy(self, D, sigma):
+        args, cD = self._d_struct(D)
+        ptrs = (ctypes.c_void_p * self.n_cells)(*[s.data_ptr() for s in sigma])
+        e = (ctypes.c_double * self.n_cells)()
+        A.check(A.lib().hfx_energy(self._h, ctypes.byref(cD), ptrs, e))
+        del args
+        return list(e)
+
+    def item_profile(self):
+        n = ctypes.c_int64()
+        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None))
+        cyc = np.zeros(n.value, np.int64)
+        units = np.zeros((n.value, 4), np.int64)
+        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), _ptr(cyc), _ptr(units)))
+        return cyc, units

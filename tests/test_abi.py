@@ -1,0 +1,127 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments before touching the device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import hfx_synth as hs
+from paper_2009_12505_amd import _abi as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hfx.h")).read()
+    return sorted(set(re.findall(r"\b(hfx_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.lib()
+    names = _declared()
+    assert set(names) == set(A.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.hfx_abi_version() == 1
+
+
+def _cstructs(w, th=None):
+    cell = w.cells[0]
+    keep = []
+    pos = np.ascontiguousarray(cell.pos.reshape(-1))
+    sp = np.ascontiguousarray(cell.species, np.int32)
+    tab = (A.Species * len(cell.species_table))(*[A.Species(a, b) for a, b in cell.species_table])
+    c = A.Cell()
+    c.n_atoms = cell.n_atoms
+    for k, v in enumerate(cell.lattice.reshape(-1)):
+        c.lattice[k] = v
+    c.pos, c.species, c.n_species, c.sp = pos.ctypes.data, sp.ctypes.data, len(cell.species_table), tab
+    keep += [pos, sp, tab]
+
+    def blk(b, data=True):
+        arrs = [np.ascontiguousarray(b.row, np.int32), np.ascontiguousarray(b.col, np.int32),
+                np.ascontiguousarray(b.R, np.int32).reshape(-1), np.ascontiguousarray(b.off, np.int64),
+                np.ascontiguousarray(b.data, np.float64)]
+        keep.extend(arrs)
+        return A.Blocks(b.n_blocks, *[a.ctypes.data for a in arrs[:4]], arrs[4].ctypes.data if data else None, 0)
+
+    t = th or w.thresholds
+    return keep, c, blk(w.C[0]), blk(w.V[0]), blk(w.D[0], False), A.Thresholds(
+        t["eps_C"], t["eps_V"], t["eps_D"], t["eps_cs_eri"], t["eps_cs_mat"])
+
+
+def _create(c, C, V, D, th, opt=None):
+    L = A.lib()
+    h = ctypes.c_void_p()
+    st = L.hfx_plan_create(1, ctypes.byref(c), ctypes.byref(C), ctypes.byref(V), ctypes.byref(D),
+                           ctypes.byref(th), None if opt is None else ctypes.byref(opt), ctypes.byref(h))
+    return st, L.hfx_last_error().decode()
+
+
+def _tiny():
+    return hs.make_workload("tiny", kind="primitive", species_table=((2, 3),), r_c=5.0, r_v=5.0, r_d=5.0)
+
+
+@pytest.mark.parametrize("bad", ["nan", "neg"])
+def test_rejects_bad_thresholds(bad):
+    w = _tiny()
+    t = dict(w.thresholds, eps_cs_mat=float("nan") if bad == "nan" else -1.0)
+    keep, c, C, V, D, th = _cstructs(w, t)
+    st, msg = _create(c, C, V, D, th)
+    assert st == A.HFX_ERR_ARG and "threshold" in msg
+
+
+def test_rejects_asymmetric_v():
+    w = _tiny()
+    V = w.V[0].compact(w.cells[0])
+    k = int(np.nonzero(V.row != V.col)[0][0])
+    V.data[V.off[k]] += 1e-3
+    w.V[0] = V
+    keep, c, C, Vs, D, th = _cstructs(w)
+    st, msg = _create(c, C, Vs, D, th)
+    assert st == A.HFX_ERR_SYMMETRY, msg
+
+
+def test_rejects_nonsymmetric_onsite_c():
+    w = _tiny()
+    C = w.C[0].compact(w.cells[0])
+    k = int(np.nonzero((C.row == C.col) & np.all(C.R == 0, axis=1))[0][0])
+    C.data[C.off[k] + 1] += 1e-2  # element [0][0][1] but not [0][1][0]
+    w.C[0] = C
+    keep, c, Cs, V, D, th = _cstructs(w)
+    st, msg = _create(c, Cs, V, D, th)
+    assert st == A.HFX_ERR_SYMMETRY, msg
+
+
+def test_rejects_out_of_range_atoms_and_duplicates():
+    w = _tiny()
+    C = w.C[0]
+    bad = hs.Blocks(C.row.copy(), C.col.copy(), C.R.copy(), C.off.copy(), C.data, "C")
+    bad.col[0] = 7
+    w.C[0] = bad
+    keep, c, Cs, V, D, th = _cstructs(w)
+    st, msg = _create(c, Cs, V, D, th)
+    assert st == A.HFX_ERR_SHAPE, msg
+    w = _tiny()
+    D = w.D[0]
+    dup = hs.Blocks(np.r_[D.row, D.row[:1]], np.r_[D.col, D.col[:1]], np.r_[D.R, D.R[:1]], np.r_[D.off, D.off[:1]],
+                    D.data, "D")
+    w.D[0] = dup
+    keep, c, Cs, V, Ds, th = _cstructs(w)
+    st, msg = _create(c, Cs, V, Ds, th)
+    assert st in (A.HFX_ERR_SHAPE, A.HFX_ERR_HIP), msg
+
+
+def test_rejects_unknown_scheduler_and_null_out():
+    w = _tiny()
+    keep, c, C, V, D, th = _cstructs(w)
+    opt = A.Options()
+    opt.scheduler = 9
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_ARG
+    L = A.lib()
+    assert L.hfx_plan_create(1, ctypes.byref(c), ctypes.byref(C), ctypes.byref(V), ctypes.byref(D),
+                             ctypes.byref(th), None, None) == A.HFX_ERR_ARG
+    assert L.hfx_build(None, None, None, None) == A.HFX_ERR_ARG
