@@ -147,6 +147,9 @@ typedef struct {               /* filled by hfx_build when non-NULL (synchronise
   double flops_tier[3];        /* executed contraction FLOPs in FP64 / FP32 / BF16x3        */
   double ms_total;             /* device time of the build (events on the plan stream)      */
   double ms_main;              /* device time of the main persistent kernel                 */
+  double phase_share[6];       /* share of the summed per-item time spent in: screening,
+                                  Y = VC and the G-side products, stage-2/3 masks, terms 3+4,
+                                  terms 1+2, item set-up                                     */
 } hfx_build_stats;
 
 typedef struct hfx_plan hfx_plan;

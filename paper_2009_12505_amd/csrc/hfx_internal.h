@@ -42,6 +42,7 @@ struct DevPlan {
   const int32_t *nao, *nabf, *cell_of, *local_of;
   // kept C blocks, grouped by row atom (c_start), sorted by distance within a row
   const double *Cbuf;
+  const double *CTbuf;  // same blocks, each transposed to [n_ao(col)][n_abf(row) * n_ao(row)]
   const long long *c_off;
   const int32_t *c_col, *c_R;
   const CNorm *c_norm;
@@ -60,6 +61,7 @@ struct DevPlan {
   const double *Dbuf;
   const double *gD;
   const uint8_t *keepD;
+  const double *gDmax;  // per cell: max over kept D blocks of sqrt||D D^T||
   double *Sbuf;
   // work
   const Item *items;
@@ -88,7 +90,8 @@ enum {
   kCntMfmaR = 15,  // MFMA instructions issued, GEMM-R
   kCntMfmaL = 16,  // MFMA instructions issued, GEMM-L
   kCntMfmaY = 17,
-  kCntN = 18
+  kCntPhase = 18,  // 6 entries: wall-clock ticks per phase, summed over items
+  kCntN = 24
 };
 
 constexpr uint32_t kPre = 1u, kCsEri = 2u, kCs1 = 4u, kCs2 = 8u, kCs3 = 16u;

@@ -34,11 +34,21 @@ constexpr int NT = 512;
 constexpr int NW = NT / 64;
 constexpr int MAXNB = 256;
 constexpr int MAXN = 32;
+constexpr int kTileWords = 8;  // column-tile bitmask words of GEMM-R (up to 512 tiles)
 
 // v_mfma_f64_16x16x4f64 lane layout (gfx950): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; element e of the result holds D[l/16 + 4e][l%16].
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// D block id of (row, col, R) for two atoms of one cell, given the cell's table base and size
+__device__ __forceinline__ int lookup_local(const DevPlan &P, int tbase, int n, int lrow, int lcol, int32_t R) {
+  const int t = tbase + lrow * n + lcol;
+  const int s = P.pstart[t], e = s + P.pcount[t];
+  for (int q = s; q < e; ++q)
+    if (P.dsort_R[q] == R) return P.dsort_id[q];
+  return -1;
 }
 
 __device__ __forceinline__ int lookup_d(const DevPlan &P, int row, int col, int32_t R) {
@@ -63,12 +73,16 @@ struct ItemLds {
   int cA, cB;  // first kept C block of A, of B
   // F side (i < nF)
   int f_atom[MAXNB], f_R[MAXNB], f_n[MAXNB], f_row0[MAXNB + 1], f_dFB[MAXNB];
+  short f_loc[MAXNB];
   long long f_dFBoff[MAXNB];
   long long f_coff[MAXNB];
   double f_gA[MAXNB], f_gF[MAXNB], f_nA[MAXNB], f_nF[MAXNB], f_Q[MAXNB];
   uint8_t f_on[MAXNB];
   // G side (j < nG)
   int g_atom[MAXNB], g_R[MAXNB], g_n[MAXNB], g_dAG[MAXNB];
+  short g_loc[MAXNB];
+  int tbase, tn;  // D lookup table of the item's cell
+  double gDmax;   // largest sqrt||D D^T|| of the item's cell (stage-1 prefilter of term 1)
   long long g_dAGoff[MAXNB];
   long long g_coff[MAXNB];
   double g_gA[MAXNB], g_gF[MAXNB], g_Q[MAXNB];
@@ -91,6 +105,8 @@ struct ItemLds {
 struct KParams {
   int rows_cap, cols_cap;  // sizes of the row/col decode tables (bytes) in dynamic LDS
   int acc_doubles;         // per-wave accumulator (doubles) in dynamic LDS
+  long long wave_off;      // offset (doubles) of the per-wave scratch regions in a slot
+  long long wave_doubles;  // size of one per-wave region
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -103,10 +119,14 @@ __device__ void phase_screen(const DevPlan &P, ItemLds &L, int *dfg, uint8_t *ma
   unsigned long long c_eri = 0, c1[4] = {0, 0, 0, 0};
   for (int p = tid; p < nF * nG; p += NT) {
     const int i = p / nG, j = p - i * nG;
-    const int dFG = lookup_d(P, L.f_atom[i], L.g_atom[j], r_sub(L.g_R[j], L.f_R[i]));
-    dfg[p] = dFG;
     uint8_t bits = 0;
+    int dFG = -1;
     if (!use_eri || L.f_Q[i] * L.g_Q[j] > eps_eri) {
+      // D_FG is needed by term 1 (operand) and term 4 (target); skip the lookup when
+      // neither can pass stage 1
+      const bool may1 = !use1 || L.f_gA[i] * L.gV * L.g_gA[j] * L.gDmax > eps;
+      const bool may4 = L.okAB && (!use1 || L.f_gF[i] * L.gV * L.g_gF[j] * P.gD[L.dAB] > eps);
+      if (may1 || may4) dFG = lookup_local(P, L.tbase, L.tn, L.f_loc[i], L.g_loc[j], r_sub(L.g_R[j], L.f_R[i]));
       bits = kCsOk;
       ++c_eri;
       // term 1: D_FG operand, target (A,B)
@@ -130,6 +150,7 @@ __device__ void phase_screen(const DevPlan &P, ItemLds &L, int *dfg, uint8_t *ma
       for (int t = 0; t < 4; ++t) c1[t] += (bits >> t) & 1;
       if (bits & 15) L.g_alive[j] = 1;
     }
+    dfg[p] = dFG;
     mask[p] = bits;
   }
   atomicAdd(&L.cnt[kCntCsEri], c_eri);
@@ -370,66 +391,105 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 
 // ---------------------------------------------------------------------------------------------
 // GEMM-R: terms 3 and 4.  Rows (F,f), K = (alpha,a), columns (G, [g | b]).
+// A wave owns a 16-row strip and walks its active 16-column tiles four at a time, so
+// each A fragment feeds four MFMAs; loads of step k+1 are issued before the MFMAs of k.
 __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
                              const uint8_t *row2i, const short *col2jj, double *accw, int acc_doubles) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int K = L.PA * L.na, nb = L.nb;
   const int mt = (L.MR + 15) >> 4, nt = (L.NR + 15) >> 4;
-  double *acc3 = accw + wave * acc_doubles;  // [16 rows][b]
+  double *acc3 = accw + wave * acc_doubles;  // [16 rows][MAXN]
   unsigned long long nmfma = 0;
+  const int kk = lane >> 4;
   for (int rt = wave; rt < mt; rt += NW) {
     for (int q = lane; q < 16 * MAXN; q += 64) acc3[q] = 0.0;
     bool any3 = false;
-    // this lane's A row
     const int ra = (rt << 4) + (lane & 15);
-    const int ia = ra < L.MR ? row2i[ra] : 0;
-    const int fa = ra - L.f_row0[ia];
-    const double *Arow = P.Cbuf + L.f_coff[ia] + fa;  // element k at Arow[k * nf]
+    const bool rowok = ra < L.MR;
+    const int ia = rowok ? row2i[ra] : 0;
+    const int fa = rowok ? ra - L.f_row0[ia] : 0;
+    const double *Arow = P.Cbuf + L.f_coff[ia] + fa;
     const int nfa = L.f_n[ia];
+    // active column tiles of this strip (exact test over each tile's 256 elements)
+    unsigned long long act[kTileWords];
+    for (int w = 0; w < kTileWords; ++w) act[w] = 0;
     for (int ct = 0; ct < nt; ++ct) {
-      // exact skip test over the 256 elements of the tile
       bool need = false;
-      {
-        const int r = (rt << 4) + (lane & 15);
+      if (rowok) {
         for (int e = 0; e < 4; ++e) {
-          const int c = (ct << 4) + ((lane >> 4) << 2) + e;
-          if (r < L.MR && c < L.NR) {
-            const int i = row2i[r], jj = col2jj[c];
-            const int j = L.a_j[jj];
+          const int c = (ct << 4) + (kk << 2) + e;
+          if (c < L.NR) {
+            const int jj = col2jj[c], j = L.a_j[jj];
             const int cc = c - L.a_col0[jj];
-            const uint8_t bits = mask[i * L.nG + j];
+            const uint8_t bits = mask[ia * L.nG + j];
             need |= (cc < L.g_n[j]) ? (bits & kT4) != 0 : (bits & kT3) != 0;
           }
         }
       }
-      if (!__any(need)) continue;
-      // this lane's B column
-      const int cb = (ct << 4) + (lane & 15);
-      const double *Bcol = nullptr;
-      int ldb = 0;
-      if (cb < L.NR) {
-        const int jj = col2jj[cb], j = L.a_j[jj];
-        const int cc = cb - L.a_col0[jj], ng = L.g_n[j];
-        if (cc < ng) {
-          Bcol = slot + L.a_t4[jj] + cc;
-          ldb = ng;
-        } else {
-          Bcol = slot + L.a_t3[jj] + (cc - ng);
-          ldb = nb;
+      if (__any(need)) act[ct >> 6] |= 1ull << (ct & 63);
+    }
+    int wi = 0;
+    unsigned long long m = act[0];
+    for (;;) {
+      int tiles[4] = {0, 0, 0, 0};
+      int n4 = 0;
+      while (n4 < 4) {
+        while (m == 0 && wi + 1 < kTileWords) m = act[++wi];
+        if (m == 0) break;
+        tiles[n4++] = (wi << 6) + __builtin_ctzll(m);
+        m &= m - 1;
+      }
+      if (n4 == 0) break;
+      const double *Bc[4];
+      int ldb[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Bc[v] = nullptr;
+        ldb[v] = 0;
+        const int cb = (tiles[v] << 4) + (lane & 15);
+        if (v < n4 && cb < L.NR) {
+          const int jj = col2jj[cb], j = L.a_j[jj];
+          const int cc = cb - L.a_col0[jj], ng = L.g_n[j];
+          if (cc < ng) {
+            Bc[v] = slot + L.a_t4[jj] + cc;
+            ldb[v] = ng;
+          } else {
+            Bc[v] = slot + L.a_t3[jj] + (cc - ng);
+            ldb[v] = nb;
+          }
         }
       }
-      d4 acc = {0, 0, 0, 0};
-      const int kk = lane >> 4;
+      d4 acc[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
+      double a_c = (rowok && kk < K) ? Arow[(long long)kk * nfa] : 0.0;
+      double b_c[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b_c[v] = (Bc[v] && kk < K) ? Bc[v][(long long)kk * ldb[v]] : 0.0;
       for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + kk;
-        const double a = (ra < L.MR && k < K) ? Arow[(long long)k * nfa] : 0.0;
-        const double b = (Bcol && k < K) ? Bcol[(long long)k * ldb] : 0.0;
-        acc = mfma64(a, b, acc);
+        const int k = k0 + 4 + kk;
+        double a_n = 0.0, b_n[4] = {0.0, 0.0, 0.0, 0.0};
+        if (k < K) {
+          if (rowok) a_n = Arow[(long long)k * nfa];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (Bc[v]) b_n[v] = Bc[v][(long long)k * ldb[v]];
+        }
+        acc[0] = mfma64(a_c, b_c[0], acc[0]);
+        if (n4 > 1) acc[1] = mfma64(a_c, b_c[1], acc[1]);
+        if (n4 > 2) acc[2] = mfma64(a_c, b_c[2], acc[2]);
+        if (n4 > 3) acc[3] = mfma64(a_c, b_c[3], acc[3]);
+        a_c = a_n;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) b_c[v] = b_n[v];
       }
-      nmfma += (K + 3) >> 2;
-      // epilogue
-      const int c = (ct << 4) + (lane & 15);
-      if (c < L.NR) {
+      nmfma += (unsigned long long)n4 * ((K + 3) >> 2);
+      // epilogue: term 4 straight to Sigma(F,G), term 3 into the strip accumulator
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (v >= n4) break;
+        const int c = (tiles[v] << 4) + (lane & 15);
+        if (c >= L.NR) continue;
         const int jj = col2jj[c], j = L.a_j[jj];
         const int cc = c - L.a_col0[jj], ng = L.g_n[j];
         for (int e = 0; e < 4; ++e) {
@@ -442,10 +502,10 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
           if (cc < ng) {
             if (bits & kT4) {
               const int d = dfg[i * L.nG + j];
-              atomicAdd(P.Sbuf + P.d_off[d] + f * ng + cc, -w * acc[e]);
+              atomicAdd(P.Sbuf + P.d_off[d] + f * ng + cc, -w * acc[v][e]);
             }
           } else if (bits & kT3) {
-            atomicAdd(&acc3[rl * MAXN + (cc - ng)], -w * acc[e]);
+            atomicAdd(&acc3[rl * MAXN + (cc - ng)], -w * acc[v][e]);
             any3 = true;
           }
         }
@@ -474,24 +534,32 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 //   P[(al,a)][(G,b)] = sum_{F,f} C_AF[al][a][f] w D_FB[f][b]   (term 2, kept units only)
 //   H1[a][b]  += sum_{al,G,g} P[(al,a)][(G,g)] Y_G[al][b][g]      -> Sigma(A,B)
 //   H2_G[a][g] = sum_{al,b}  P[(al,a)][(G,b)] Y_G[al][b][g]      -> Sigma(A,G)
+// A wave owns a 32-column strip.  The masked D panel of the strip (rows: the F's with a
+// kept unit in the strip) is staged once in the wave's scratch; the C operand is read
+// from the per-block transposed copy C^T[f][(al,a)] so a fragment is 16 consecutive
+// doubles; each wave computes 64x32 of P per pass (8 MFMAs per K step).  The Y
+// contractions of the epilogue are MFMA products over K = (al, column).
 __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
-                             const uint8_t *row2i, const short *col2jj, double *accw, int acc_doubles) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int M = L.PA * L.na, na = L.na, nb = L.nb, nF = L.nF;
-  const int mt = (M + 15) >> 4, nt = (L.NR + 15) >> 4;
-  double *acc2 = accw + wave * acc_doubles;  // [jj - jj0][a][g]
-  double *tl = L.tile[wave];
+                             const short *col2jj, double *wreg, int rows_cap) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int M = L.PA * L.na, na = L.na, nb = L.nb, nF = L.nF, PA = L.PA;
+  const int ns = (L.NR + 31) >> 5;
+  double *Bp = wreg;                                                    // [rows_cap][32]
+  long long *kaddr = reinterpret_cast<long long *>(Bp + (long long)rows_cap * 32);  // [rows_cap]
+  double *Pb = reinterpret_cast<double *>(kaddr + rows_cap);            // [M][32]
+  const double *CT = P.CTbuf;
   unsigned long long nmfma = 0;
-  for (int ct = wave; ct < nt; ct += NW) {
-    const int c0 = ct << 4;
-    const int c1 = min(c0 + 16, L.NR);
+  const int kk = lane >> 4, l16 = lane & 15;
+  for (int cs = tid >> 6; cs < ns; cs += NW) {
+    const int c0 = cs << 5, c1 = min(c0 + 32, L.NR);
     const int jj0 = col2jj[c0], jj1 = col2jj[c1 - 1];
-    // which halves of which G appear in this column tile
-    // F set: i with any kept term-1 unit (g-half present) or term-2 unit (b-half present)
     unsigned long long fset[4] = {0, 0, 0, 0};
+    bool t1any = false;
+    unsigned t2any = 0;
     for (int base = 0; base < nF; base += 64) {
       const int i = base + lane;
-      bool hit = false;
+      bool hit = false, h1 = false;
+      unsigned h2 = 0;
       if (i < nF) {
         for (int jj = jj0; jj <= jj1; ++jj) {
           const int j = L.a_j[jj];
@@ -499,114 +567,149 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
           const bool hasg = max(c0, g0) < min(c1, gb);
           const bool hasb = max(c0, gb) < min(c1, g1);
           const uint8_t bits = mask[i * L.nG + j];
-          hit |= (hasg && (bits & kT1)) || (hasb && (bits & kT2));
+          if (hasg && (bits & kT1)) h1 = true;
+          if (hasb && (bits & kT2)) h2 |= 1u << (jj - jj0);
         }
+        hit = h1 || h2;
       }
       fset[base >> 6] = __ballot(hit);
+      t1any |= __any(h1);
+      for (int q = 0; q <= jj1 - jj0; ++q)
+        if (__any((h2 >> q) & 1u)) t2any |= 1u << q;
     }
     if (!(fset[0] | fset[1] | fset[2] | fset[3])) continue;
-    const int nj = jj1 - jj0 + 1;
-    for (int q = lane; q < nj * na * MAXN; q += 64) acc2[q] = 0.0;
-    // this lane's B column
-    const int cb = c0 + (lane & 15);
-    int jjb = 0, jb = 0, ccb = 0, ngb = 0;
-    bool colok = cb < L.NR;
-    if (colok) {
-      jjb = col2jj[cb];
-      jb = L.a_j[jjb];
-      ccb = cb - L.a_col0[jjb];
-      ngb = L.g_n[jb];
-    }
-    bool any1 = false, any2 = false;
-    for (int rt = 0; rt < mt; ++rt) {
-      const int r = (rt << 4) + (lane & 15);  // A row (al,a)
-      const bool rowok = r < M;
-      d4 acc = {0, 0, 0, 0};
-      int kdone = 0;
-      bool did = false;
-      for (int w64 = 0; w64 < 4; ++w64) {
-        unsigned long long m = fset[w64];
-        while (m) {
-          const int i = (w64 << 6) + __builtin_ctzll(m);
-          m &= m - 1;
-          const int kb = L.f_row0[i], ke = L.f_row0[i + 1];
-          int k0 = max(kb & ~3, kdone);
-          for (; k0 < ke; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            double a = 0.0, b = 0.0;
-            if (k < L.MR) {
-              const int ik = row2i[k], f = k - L.f_row0[ik];
-              if (rowok) a = P.Cbuf[L.f_coff[ik] + (long long)r * L.f_n[ik] + f];
-              if (colok) {
-                const uint8_t bits = mask[ik * L.nG + jb];
-                const double w = unit_weight(L, ik, jb);
-                if (ccb < ngb) {
-                  if (bits & kT1) b = w * P.Dbuf[P.d_off[dfg[ik * L.nG + jb]] + f * ngb + ccb];
-                } else if (bits & kT2) {
-                  b = w * P.Dbuf[L.f_dFBoff[ik] + f * nb + (ccb - ngb)];
-                }
-              }
+    // stage the masked D panel and the C^T row addresses of the strip's F set
+    int kc = 0;
+    long long first = -1;
+    for (int w64 = 0; w64 < 4; ++w64) {
+      unsigned long long mm = fset[w64];
+      while (mm) {
+        const int i = (w64 << 6) + __builtin_ctzll(mm);
+        mm &= mm - 1;
+        const int nf = L.f_n[i];
+        if (first < 0) first = L.f_coff[i];
+        for (int e = lane; e < nf * 32; e += 64) {
+          const int f = e >> 5, cl = e & 31, c = c0 + cl;
+          double val = 0.0;
+          if (c < c1) {
+            const int jj = col2jj[c], j = L.a_j[jj];
+            const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+            const uint8_t bits = mask[i * L.nG + j];
+            const double w = unit_weight(L, i, j);
+            if (cc < ng) {
+              if (bits & kT1) val = w * P.Dbuf[P.d_off[dfg[i * L.nG + j]] + f * ng + cc];
+            } else if (bits & kT2) {
+              val = w * P.Dbuf[L.f_dFBoff[i] + f * nb + (cc - ng)];
             }
-            acc = mfma64(a, b, acc);
-            ++nmfma;
           }
-          kdone = max(kdone, k0);
-          did = true;
+          Bp[(long long)(kc + f) * 32 + cl] = val;
         }
+        if (lane < nf) kaddr[kc + lane] = L.f_coff[i] + (long long)lane * M;
+        kc += nf;
       }
-      if (!did) continue;
-      // stage the tile in LDS: tl[row][col]
-      for (int e = 0; e < 4; ++e) tl[((lane >> 4) + 4 * e) * 16 + (lane & 15)] = acc[e];
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      // epilogue: 16 rows x MAXN outputs
-      for (int q = lane; q < 16 * MAXN; q += 64) {
-        const int rl = q / MAXN, o = q - rl * MAXN;
-        const int rr = (rt << 4) + rl;
-        if (rr >= M) continue;
-        const int al = rr / na, a = rr - al * na;
-        double s1 = 0.0;
-        int jcur = -1;
-        double s2 = 0.0;
-        for (int cl = 0; cl < c1 - c0; ++cl) {
-          const int c = c0 + cl;
-          const int jj = col2jj[c], j = L.a_j[jj];
-          const int cc = c - L.a_col0[jj], ng = L.g_n[j];
-          const double pv = tl[rl * 16 + cl];
-          if (pv == 0.0) continue;
-          const double *Y = slot + L.a_y[jj] + (long long)al * nb * ng;
-          if (cc < ng) {
-            if (o < nb) s1 += pv * Y[o * ng + cc];
-          } else {
-            if (jj != jcur) {
-              if (jcur >= 0 && s2 != 0.0) atomicAdd(&acc2[((jcur - jj0) * na + a) * MAXN + o], s2);
-              jcur = jj;
-              s2 = 0.0;
-            }
-            if (o < ng) s2 += pv * Y[(cc - ng) * ng + o];
-          }
-        }
-        if (jcur >= 0 && s2 != 0.0) {
-          atomicAdd(&acc2[((jcur - jj0) * na + a) * MAXN + o], s2);
-          any2 = true;
-        }
-        if (s1 != 0.0) {
-          atomicAdd(&L.H1[a * MAXN + o], s1);
-          any1 = true;
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
     }
-    (void)any1;
-    // flush term 2 of this column tile: Sigma(A,G)[a][g]
-    if (__any(any2)) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      for (int q = lane; q < nj * na * MAXN; q += 64) {
-        const int jl = q / (na * MAXN), a = (q / MAXN) % na, g = q % MAXN;
-        const double v = acc2[q];
-        if (v == 0.0) continue;
-        const int j = L.a_j[jj0 + jl];
-        if (g < L.g_n[j]) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * L.g_n[j] + g, -v);
+    const int Kc = (kc + 3) & ~3;
+    for (int e = lane; e < (Kc - kc) * 32; e += 64) Bp[(long long)kc * 32 + e] = 0.0;
+    if (lane < Kc - kc) kaddr[kc + lane] = first;
+    __threadfence_block();
+    // P strip = C_A x panel, 64 rows per pass
+    for (int rg = 0; rg < M; rg += 64) {
+      d4 acc[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = d4{0, 0, 0, 0};
+      int rr[4];
+      bool rok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rr[u] = rg + 16 * u + l16;
+        rok[u] = rr[u] < M;
+      }
+      double a_c[4], b_c[2];
+      {
+        const long long bs = kaddr[kk];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a_c[u] = rok[u] ? CT[bs + rr[u]] : 0.0;
+        b_c[0] = Bp[kk * 32 + l16];
+        b_c[1] = Bp[kk * 32 + 16 + l16];
+      }
+      for (int k0 = 0; k0 < Kc; k0 += 4) {
+        const int k = k0 + 4 + kk;
+        double a_n[4] = {0.0, 0.0, 0.0, 0.0}, b_n[2] = {0.0, 0.0};
+        if (k0 + 4 < Kc) {
+          const long long bs = kaddr[k];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (rok[u]) a_n[u] = CT[bs + rr[u]];
+          b_n[0] = Bp[(long long)k * 32 + l16];
+          b_n[1] = Bp[(long long)k * 32 + 16 + l16];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[u][0] = mfma64(a_c[u], b_c[0], acc[u][0]);
+          acc[u][1] = mfma64(a_c[u], b_c[1], acc[u][1]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a_c[u] = a_n[u];
+        b_c[0] = b_n[0];
+        b_c[1] = b_n[1];
+      }
+      nmfma += 8ull * (Kc >> 2);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = rg + 16 * u + kk + 4 * e;
+          if (row < M) {
+            Pb[(long long)row * 32 + l16] = acc[u][0][e];
+            Pb[(long long)row * 32 + 16 + l16] = acc[u][1][e];
+          }
+        }
+    }
+    __threadfence_block();
+    // term 1: H1[a][b] += sum_{al, c in g-halves} P[(al,a)][c] Y_G(c)[al][b][g(c)]
+    if (t1any) {
+      d4 h = {0, 0, 0, 0};
+      for (int al = 0; al < PA; ++al)
+        for (int cg = 0; cg < 32; cg += 4) {
+          const int cl = cg + kk, c = c0 + cl;
+          double av = 0.0, bv = 0.0;
+          if (c < c1) {
+            const int jj = col2jj[c], j = L.a_j[jj];
+            const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+            if (cc < ng) {
+              if (l16 < na) av = Pb[(long long)(al * na + l16) * 32 + cl];
+              if (l16 < nb) bv = slot[L.a_y[jj] + ((long long)al * nb + l16) * ng + cc];
+            }
+          }
+          h = mfma64(av, bv, h);
+        }
+      nmfma += (unsigned long long)PA * 8;
+      for (int e = 0; e < 4; ++e) {
+        const int a = kk + 4 * e;
+        if (a < na && l16 < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + l16], h[e]);
+      }
+    }
+    // term 2: H2_G[a][g] = sum_{al, b in G's b-half} P[(al,a)][(G,b)] Y_G[al][b][g]
+    for (int q = 0; q <= jj1 - jj0; ++q) {
+      if (!((t2any >> q) & 1u)) continue;
+      const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
+      const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
+      const int bc0 = max(c0, gb), bc1 = min(c1, g1);
+      d4 h = {0, 0, 0, 0};
+      for (int al = 0; al < PA; ++al)
+        for (int cb = bc0; cb < bc1; cb += 4) {
+          const int c = cb + kk;
+          double av = 0.0, bv = 0.0;
+          if (c < bc1) {
+            if (l16 < na) av = Pb[(long long)(al * na + l16) * 32 + (c - c0)];
+            if (l16 < ng) bv = slot[L.a_y[jj] + ((long long)al * nb + (c - gb)) * ng + l16];
+          }
+          h = mfma64(av, bv, h);
+        }
+      nmfma += (unsigned long long)PA * ((bc1 - bc0 + 3) >> 2);
+      for (int e = 0; e < 4; ++e) {
+        const int a = kk + 4 * e;
+        if (a < na && l16 < ng && h[e] != 0.0) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * ng + l16, -h[e]);
       }
     }
   }
@@ -646,6 +749,10 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       L.nG = P.c_start[it.B + 1] - L.cB;
       L.gV = P.gV[it.vid];
       L.voff = P.v_off[it.vid];
+      const int cell = P.cell_of[it.A];
+      L.tbase = P.ptab_off[cell];
+      L.tn = P.cell_natoms[cell];
+      L.gDmax = P.gDmax[cell];
       L.dAB = lookup_d(P, it.A, it.B, it.rb);
       L.okAB = L.dAB >= 0 && P.keepD[L.dAB];
     }
@@ -666,6 +773,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       L.f_nF[i] = cn.nF;
       L.f_Q[i] = cn.Q;
       L.f_on[i] = (F == L.A && r_zero(RF));
+      L.f_loc[i] = (short)P.local_of[F];
       const int d = lookup_d(P, F, L.B, r_sub(L.rb, RF));
       L.f_dFB[i] = d;
       L.f_dFBoff[i] = d >= 0 ? P.d_off[d] : 0;
@@ -683,6 +791,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       L.g_gF[j] = cn.gF;
       L.g_Q[j] = cn.Q;
       L.g_on[j] = (G == L.B && r_zero(P.c_R[cg]));
+      L.g_loc[j] = (short)P.local_of[G];
       const int d = lookup_d(P, L.A, G, RG);
       L.g_dAG[j] = d;
       L.g_dAGoff[j] = d >= 0 ? P.d_off[d] : 0;
@@ -708,8 +817,18 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     double *E2 = slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3);
     double *gbase_d = E2 + L.nF * L.nb * L.nb;
     __syncthreads();
+    long long tp = wall_clock64();
+    auto tick = [&](int ph) {
+      if (tid == 0) {
+        const long long t = wall_clock64();
+        L.cnt[kCntPhase + ph] += (unsigned long long)(t - tp);
+        tp = t;
+      }
+    };
+    tick(5);
     phase_screen(P, L, dfg, mask);
     __syncthreads();
+    tick(0);
     // compact alive G and lay out their buffers
     if (tid == 0) {
       int n = 0, col = 0;
@@ -742,6 +861,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     }
     __syncthreads();
     for (int jj = 0; jj < L.nGa; ++jj) phase_gside_one(P, L, slot, jj);
+    tick(1);
     phase_masks(P, L, slot, dfg, mask, E2);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
@@ -767,12 +887,16 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       col2jj[c] = (short)lo;
     }
     __syncthreads();
+    tick(2);
     if (L.nGa > 0) {
       phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, accw, kp.acc_doubles);
       __syncthreads();
-      phase_gemm_l(P, L, slot, dfg, mask, row2i, col2jj, accw, kp.acc_doubles);
+      tick(3);
+      phase_gemm_l(P, L, slot, dfg, mask, col2jj, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles,
+                   kp.rows_cap);
     }
     __syncthreads();
+    tick(4);
     // flush term 1: Sigma(A,B)
     if (L.dAB >= 0)
       for (int q = tid; q < L.na * L.nb; q += NT) {
@@ -938,6 +1062,23 @@ __global__ __launch_bounds__(256) void k_vnorm(const double *__restrict__ Vbuf, 
   if (threadIdx.x == 0) gV[vb] = sqrt(sqrt(s_acc[0]));
 }
 
+// plan-time: per-block transposed copy of C, CT[f][(alpha,a)] = C[(alpha,a)][f]
+__global__ __launch_bounds__(256) void k_ctrans(const double *__restrict__ Cbuf, const long long *__restrict__ c_off,
+                                                const int *__restrict__ c_row, const int *__restrict__ c_col,
+                                                const int *__restrict__ nao, const int *__restrict__ nabf, int nC,
+                                                double *__restrict__ CT) {
+  const int cb = blockIdx.x;
+  if (cb >= nC) return;
+  const int A = c_row[cb], F = c_col[cb];
+  const int M = nabf[A] * nao[A], nf = nao[F];
+  const double *C = Cbuf + c_off[cb];
+  double *T = CT + c_off[cb];
+  for (int q = threadIdx.x; q < M * nf; q += 256) {
+    const int f = q / M, r = q - f * M;
+    T[q] = C[r * nf + f];
+  }
+}
+
 // per build: gather D blocks from the caller layout into the compact layout
 __global__ void k_dgather(const double *__restrict__ src, const long long *__restrict__ src_off,
                           const long long *__restrict__ dst_off, int nD, long long base, double *__restrict__ dst) {
@@ -975,6 +1116,24 @@ __global__ __launch_bounds__(64) void k_dprep(const double *__restrict__ Dbuf, c
     gD[b] = sqrt(sqrt(acc));
     keepD[b] = pre ? (mx > eps_D) : 1;
   }
+}
+
+// per build: max over the kept D blocks of each cell of sqrt||D D^T|| (a conservative
+// stand-in for gD in a stage-1 prefilter)
+__global__ __launch_bounds__(256) void k_dmax(const double *__restrict__ gD, const uint8_t *__restrict__ keepD,
+                                              const long long *__restrict__ dbase, double *__restrict__ gDmax) {
+  const int c = blockIdx.x;
+  __shared__ double sm[256];
+  double m = 0;
+  for (long long b = dbase[c] + threadIdx.x; b < dbase[c + 1]; b += 256)
+    if (keepD[b]) m = fmax(m, gD[b]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gDmax[c] = sm[0];
 }
 
 __global__ void k_zero(double *__restrict__ p, long long n) {
@@ -1020,9 +1179,9 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ D, co
 
 // ---------------------------------------------------------------------------------------------
 // launch wrappers (host side)
-hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles,
-                       hipStream_t s) {
-  KParams kp{rows_cap, cols_cap, acc_doubles};
+hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles, long long wave_off,
+                       long long wave_doubles, hipStream_t s) {
+  KParams kp{rows_cap, cols_cap, acc_doubles, wave_off, wave_doubles};
   const size_t dyn = (size_t)rows_cap + 2 * (size_t)cols_cap + (size_t)NW * acc_doubles * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
   if (e != hipSuccess) return e;
@@ -1039,6 +1198,11 @@ int main_nwaves() { return NW; }
 hipError_t launch_cnorm(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
                         const int *nao, const int *nabf, int nC, CNorm *out, hipStream_t s) {
   if (nC > 0) hipLaunchKernelGGL(k_cnorm, dim3(nC), dim3(256), 0, s, Cbuf, c_off, c_row, c_col, nao, nabf, nC, out);
+  return hipGetLastError();
+}
+hipError_t launch_ctrans(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
+                         const int *nao, const int *nabf, int nC, double *CT, hipStream_t s) {
+  if (nC > 0) hipLaunchKernelGGL(k_ctrans, dim3(nC), dim3(256), 0, s, Cbuf, c_off, c_row, c_col, nao, nabf, nC, CT);
   return hipGetLastError();
 }
 hipError_t launch_cq(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
@@ -1064,6 +1228,11 @@ hipError_t launch_dprep(const double *Dbuf, const long long *d_off, const int *d
   if (nD > 0)
     hipLaunchKernelGGL(k_dprep, dim3((nD + 3) / 4), dim3(64), 0, s, Dbuf, d_off, d_row, d_col, nao, nD, eps_D, pre, gD,
                        keepD);
+  return hipGetLastError();
+}
+hipError_t launch_dmax(const double *gD, const uint8_t *keepD, const long long *dbase, double *gDmax, int n_cells,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_dmax, dim3(n_cells), dim3(256), 0, s, gD, keepD, dbase, gDmax);
   return hipGetLastError();
 }
 hipError_t launch_zero(double *p, long long n, hipStream_t s) {

@@ -20,7 +20,10 @@
 #include "hfx_internal.h"
 
 namespace hfx {
-hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles, hipStream_t s);
+hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles, long long wave_off,
+                       long long wave_doubles, hipStream_t s);
+hipError_t launch_ctrans(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
+                         const int *nao, const int *nabf, int nC, double *CT, hipStream_t s);
 size_t main_static_lds();
 int main_threads();
 int main_maxnb();
@@ -38,6 +41,8 @@ hipError_t launch_dgather(const double *src, const long long *src_off, const lon
 hipError_t launch_dprep(const double *Dbuf, const long long *d_off, const int *d_row, const int *d_col,
                         const int *nao, int nD, double eps_D, int pre, double *gD, uint8_t *keepD, hipStream_t s);
 hipError_t launch_zero(double *p, long long n, hipStream_t s);
+hipError_t launch_dmax(const double *gD, const uint8_t *keepD, const long long *dbase, double *gDmax, int n_cells,
+                       hipStream_t s);
 hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, hipStream_t s);
 hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s);
 }  // namespace hfx
@@ -104,6 +109,8 @@ struct hfx_plan {
   std::vector<long long *> d_inoff_dev;       // per cell, device copy of caller offsets
   std::vector<int32_t> d_row_g, d_col_g;      // global atom ids per global D id
   int32_t *d_row_dev = nullptr, *d_col_dev = nullptr;
+  long long *dbase_dev = nullptr;
+  double *gDmax_dev = nullptr;
   int64_t nD = 0;
 
   // items
@@ -113,6 +120,7 @@ struct hfx_plan {
 
   DevPlan dp{};
   int n_slots = 0, rows_cap = 0, cols_cap = 0, acc_doubles = 0;
+  long long wave_off = 0, wave_doubles = 0;
   double *part = nullptr;  // energy partial sums
   int part_blocks = 1024;
   double *staging = nullptr;  // pinned host staging for D
@@ -556,10 +564,12 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   }
   p->rows_cap = (p->rows_cap + 15) / 16 * 16 + 16;
   p->cols_cap = (p->cols_cap + 15) / 16 * 16 + 16;
-  if (p->rows_cap > 255 * 64 || p->cols_cap > 32767)
+  if (p->rows_cap > 255 * 64 || p->cols_cap > 16 * 64 * 8)
     return fail(HFX_ERR_UNSUPPORTED, "neighbour lists too long for the decode tables");
   const int64_t nfg = (int64_t)max_nbr * max_nbr;
-  const int64_t slot = (nfg + 1) / 2 + (nfg + 7) / 8 + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
+  p->wave_off = (nfg + 1) / 2 + (nfg + 7) / 8 + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
+  p->wave_doubles = ((int64_t)p->rows_cap * 33 + (int64_t)max_p * max_n * 32 + 64 + 31) / 32 * 32;
+  const int64_t slot = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
   const int J = 16 / (2 * min_n) + 2;
   p->acc_doubles = std::max(16 * main_maxn(), J * max_n * main_maxn());
   const size_t lds = main_static_lds() + (size_t)p->rows_cap + 2 * (size_t)p->cols_cap +
@@ -582,7 +592,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   hfx_status st;
   int32_t *d_nao, *d_nabf, *d_cellof, *d_localof, *d_cstart, *d_ccol, *d_cR, *d_crow, *d_vrow, *d_vcol, *d_qsrc;
   long long *d_coff, *d_voff, *d_doff;
-  double *d_C, *d_V, *d_gV, *d_gD, *d_D, *d_S, *d_scr;
+  double *d_C, *d_CT, *d_V, *d_gV, *d_gD, *d_D, *d_S, *d_scr;
   CNorm *d_cn;
   int32_t *d_ptoff, *d_pstart, *d_pcount, *d_dsR, *d_dsid, *d_cellnat, *d_order, *d_drow, *d_dcol;
   uint8_t *d_keepD;
@@ -596,6 +606,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       (st = p->upload(&d_cellof, p->cell_of)) || (st = p->upload(&d_localof, p->local_of)) ||
       (st = p->upload(&d_cstart, c_start)) || (st = p->upload(&d_ccol, c_col)) || (st = p->upload(&d_crow, c_row)) ||
       (st = p->upload(&d_cR, c_Rp)) || (st = p->upload(&d_coff, c_off)) || (st = p->upload(&d_C, cstage)) ||
+      (st = p->dalloc(&d_CT, cstage.size())) ||
       (st = p->upload(&d_vrow, v_row)) || (st = p->upload(&d_vcol, v_col)) || (st = p->upload(&d_voff, v_off)) ||
       (st = p->upload(&d_V, vstage)) || (st = p->upload(&d_qsrc, qsrc)) || (st = p->dalloc(&d_cn, nC)) ||
       (st = p->dalloc(&d_gV, nV)) || (st = p->upload(&d_ptoff, ptab_off)) || (st = p->upload(&d_pstart, pstart)) ||
@@ -613,6 +624,10 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   cstage.shrink_to_fit();
   vstage.clear();
   vstage.shrink_to_fit();
+  {
+    std::vector<long long> db(p->dbase.begin(), p->dbase.end());
+    if ((st = p->upload(&p->dbase_dev, db)) || (st = p->dalloc(&p->gDmax_dev, n_cells))) return st;
+  }
   p->d_row_dev = d_drow;
   p->d_col_dev = d_dcol;
   p->d_inoff_dev.resize(n_cells);
@@ -629,6 +644,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   P.cell_of = d_cellof;
   P.local_of = d_localof;
   P.Cbuf = d_C;
+  P.CTbuf = d_CT;
   P.c_off = d_coff;
   P.c_col = d_ccol;
   P.c_R = d_cR;
@@ -647,6 +663,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   P.Dbuf = d_D;
   P.gD = d_gD;
   P.keepD = d_keepD;
+  P.gDmax = p->gDmax_dev;
   P.Sbuf = d_S;
   P.items = d_items;
   P.order = d_order;
@@ -666,6 +683,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
 
   // ---- plan-time kernels: C norms, CS-ERI factors, V norms
   HIPCHK(p, launch_cnorm(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_cn, p->stream));
+  HIPCHK(p, launch_ctrans(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_CT, p->stream));
   HIPCHK(p, launch_cq(d_C, d_coff, d_crow, d_ccol, d_V, d_voff, d_qsrc, d_nao, d_nabf, nC, d_cn, p->stream));
   HIPCHK(p, launch_vnorm(d_V, d_voff, d_vrow, d_vcol, d_nabf, nV, d_gV, p->stream));
   HIPCHK(p, hipEventCreate(&p->ev0));
@@ -742,10 +760,12 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
   HIPCHK(p, launch_dprep(P.Dbuf, P.d_off, p->d_row_dev, p->d_col_dev, P.nao, (int)p->nD, p->th.eps_D,
                          (p->stages & HFX_SCREEN_PRE) ? 1 : 0, const_cast<double *>(P.gD),
                          const_cast<uint8_t *>(P.keepD), p->stream));
+  HIPCHK(p, launch_dmax(P.gD, P.keepD, p->dbase_dev, p->gDmax_dev, p->n_cells, p->stream));
   HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
   HIPCHK(p, launch_reset(P.ticket, P.counters, p->stream));
   HIPCHK(p, hipEventRecord(p->ev1, p->stream));
-  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->acc_doubles, p->stream));
+  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->acc_doubles, p->wave_off, p->wave_doubles,
+                                          p->stream));
   HIPCHK(p, hipEventRecord(p->ev2, p->stream));
   for (int c = 0; c < p->n_cells; ++c) {
     const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
@@ -771,6 +791,9 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     HIPCHK(p, hipEventElapsedTime(&ms1, p->ev1, p->ev2));
     stats->ms_total = ms0;
     stats->ms_main = ms1;
+    double tot = 0;
+    for (int k = 0; k < 6; ++k) tot += (double)cnt[kCntPhase + k];
+    for (int k = 0; k < 6; ++k) stats->phase_share[k] = tot > 0 ? (double)cnt[kCntPhase + k] / tot : 0.0;
   }
   return HFX_OK;
 }
