@@ -141,10 +141,13 @@ typedef struct {               /* filled by hfx_build when non-NULL (synchronise
   int64_t kept[3][4];          /* [stage 1..3][term 1..4] units surviving each stage        */
   int64_t items;               /* <A,B> work items                                          */
   int64_t g_alive;             /* (A,B,G) triples whose Y = V C was formed                  */
-  double flops_contract;       /* FP64-equivalent FLOPs of the contractions as executed     */
-  double flops_paper;          /* FLOPs of the same kept units counted per unit as in
-                                  Algorithm 3 (Y once per (A,B,G), T3/T4 once per G)        */
-  double flops_tier[3];        /* executed contraction FLOPs in FP64 / FP32 / BF16x3        */
+  double flops_contract;       /* useful FLOPs of the contractions this library performs for
+                                  the kept units (padding and screened-out work excluded)   */
+  double flops_paper;          /* FLOPs of the same kept units counted as in Algorithm 3:
+                                  T and Htilde per unit, Y, T3, T4 once per (A,B,G)          */
+  double flops_tier[3];        /* flops_contract split by precision: FP64 / FP32 / BF16x3   */
+  double mfma_flops[3];        /* matrix-core FLOPs issued (with padding): G side and masks,
+                                  terms 3+4, terms 1+2                                       */
   double ms_total;             /* device time of the build (events on the plan stream)      */
   double ms_main;              /* device time of the main persistent kernel                 */
   double phase_share[6];       /* share of the summed per-item time spent in: screening,

@@ -78,6 +78,7 @@ struct DevPlan {
   // counters
   unsigned int *ticket;
   unsigned long long *counters;  // see kCnt* below
+  double *flops;                 // [0] Algorithm-3 count, [1] this kernel's useful count
   long long *item_cycles;        // per item (plan order)
   int *item_units;               // per item x 4
 };

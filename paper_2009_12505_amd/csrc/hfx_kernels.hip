@@ -62,7 +62,7 @@ __device__ __forceinline__ int lookup_d(const DevPlan &P, int row, int col, int3
 }
 
 // term bits of the per-(F,G) masks
-constexpr uint8_t kT1 = 1, kT2 = 2, kT3 = 4, kT4 = 8, kCsOk = 16, kPend1 = 32;
+constexpr uint8_t kT1 = 1, kT2 = 2, kT3 = 4, kT4 = 8, kCsOk = 16, kPend1 = 32, kPend2 = 64;
 
 struct ItemLds {
   int A, B, rb, PA, PB, na, nb, nF, nG, nGa, MR, NR, J;
@@ -99,6 +99,7 @@ struct ItemLds {
   double sq[2 * MAXN];
   double tile[NW][256];
   unsigned long long cnt[kCntN];
+  double flops[2];
   int scratch_top;
 };
 
@@ -159,136 +160,225 @@ __device__ void phase_screen(const DevPlan &P, ItemLds &L, int *dfg, uint8_t *ma
 }
 
 // ---------------------------------------------------------------------------------------------
-// G side for one alive G: Y = V_AB C_BG, norms, T3, T4, Gram matrices
-__device__ void phase_gside_one(const DevPlan &P, ItemLds &L, double *slot, int jj) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// one 16x16 FP64 MFMA tile product over K with a one-step load prefetch;
+// fa(row, k) and fb(k, col) return 0 outside the operands
+template <class FA, class FB>
+__device__ __forceinline__ d4 tile_mm(int K, FA fa, FB fb) {
+  const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
+  d4 acc = {0, 0, 0, 0};
+  double a_c = fa(l16, kk), b_c = fb(kk, l16);
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + 4 + kk;
+    double a_n = 0.0, b_n = 0.0;
+    if (k0 + 4 < K) {
+      a_n = fa(l16, k);
+      b_n = fb(k, l16);
+    }
+    acc = mfma64(a_c, b_c, acc);
+    a_c = a_n;
+    b_c = b_n;
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// G side for one alive G, by one wave: Y = V_AB C_BG, T4 = D_AB Y, T3 = Y D_AG^T (per alpha),
+// the Gram matrices N1[b] = Y_b^T Y_b and M2[g] = Y_g^T Y_g, and the slice norms of stages 2, 3
+__device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, const double *Vsrc) {
+  const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
   const int j = L.a_j[jj];
   const int PA = L.PA, PB = L.PB, na = L.na, nb = L.nb, ng = L.g_n[j];
   const int N = nb * ng;
-  const double *V = P.Vbuf + L.voff;
   const double *C = P.Cbuf + L.g_coff[j];
   double *Y = slot + L.a_y[jj];
-  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]
-  {
-    const int mt = (PA + 15) >> 4, nt = (N + 15) >> 4;
-    for (int t = wave; t < mt * nt; t += NW) {
-      const int m0 = (t / nt) << 4, n0 = (t % nt) << 4;
-      const int row = m0 + (lane & 15), col = n0 + (lane & 15), kk = lane >> 4;
-      d4 acc = {0, 0, 0, 0};
+  unsigned long long nm = 0;
+  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]; four alpha tiles share each C fragment
+  const int mt = (PA + 15) >> 4, nt = (N + 15) >> 4;
+  for (int rg = 0; rg < mt; rg += 4) {
+    for (int ct = 0; ct < nt; ++ct) {
+      const int col = (ct << 4) + l16;
+      const bool cok = col < N;
+      d4 acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
+      int row[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) row[u] = ((rg + u) << 4) + l16;
+      double b_c = (cok && kk < PB) ? C[(long long)kk * N + col] : 0.0;
       for (int k0 = 0; k0 < PB; k0 += 4) {
         const int k = k0 + kk;
-        const double a = (row < PA && k < PB) ? V[row * PB + k] : 0.0;
-        const double b = (k < PB && col < N) ? C[(long long)k * N + col] : 0.0;
-        acc = mfma64(a, b, acc);
+        const int kn = k + 4;
+        const double b_n = (k0 + 4 < PB && cok && kn < PB) ? C[(long long)kn * N + col] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (rg + u >= mt) break;
+          const double a = (row[u] < PA && k < PB) ? Vsrc[row[u] * PB + k] : 0.0;
+          acc[u] = mfma64(a, b_c, acc[u]);
+        }
+        b_c = b_n;
       }
-      const int c = n0 + (lane & 15);
-      for (int e = 0; e < 4; ++e) {
-        const int r = m0 + (lane >> 4) + 4 * e;
-        if (r < PA && c < N) Y[(long long)r * N + c] = acc[e];
-      }
+      nm += (unsigned long long)min(4, mt - rg) * ((PB + 3) >> 2);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = ((rg + u) << 4) + kk + 4 * e;
+          if (rg + u < mt && r < PA && cok) Y[(long long)r * N + col] = acc[u][e];
+        }
     }
   }
-  // D_AG for this G
-  const int dAG = L.g_dAG[j];
-  const bool okAG = dAG >= 0 && P.keepD[dAG];
-  if (okAG)
-    for (int q = tid; q < na * ng; q += NT) L.DAG[q] = P.Dbuf[P.d_off[dAG] + q];
-  if (tid < 2 * MAXN) L.sq[tid] = 0.0;
-  __syncthreads();
-  // Gram matrices: N1[b][g][g'] = sum_al Y[al][b][g] Y[al][b][g'];  M2[g][b][b'] = sum_al Y[al][b][g] Y[al][b'][g]
-  double *N1 = slot + L.a_n1[jj];
-  double *M2 = slot + L.a_m2[jj];
-  for (int q = tid; q < nb * ng * ng; q += NT) {
-    const int b = q / (ng * ng), g = (q / ng) % ng, g2 = q % ng;
-    double s = 0;
-    for (int al = 0; al < PA; ++al) s += Y[(long long)al * N + b * ng + g] * Y[(long long)al * N + b * ng + g2];
-    N1[q] = s;
-  }
-  for (int q = tid; q < ng * nb * nb; q += NT) {
-    const int g = q / (nb * nb), b = (q / nb) % nb, b2 = q % nb;
-    double s = 0;
-    for (int al = 0; al < PA; ++al) s += Y[(long long)al * N + b * ng + g] * Y[(long long)al * N + b2 * ng + g];
-    M2[q] = s;
-  }
-  // T4[al*na+a][g] = sum_b Y[al][b][g] D_AB[a][b]
+  __threadfence_block();
+  // T4[(al,a)][g] = sum_b D_AB[a][b] Y[al][b][g]
+  double t4max = 0.0;
   if (L.okAB) {
     double *T4 = slot + L.a_t4[jj];
-    for (int q = tid; q < PA * na * ng; q += NT) {
-      const int al = q / (na * ng), a = (q / ng) % na, g = q % ng;
-      double s = 0;
-      for (int b = 0; b < nb; ++b) s += Y[(long long)al * N + b * ng + g] * L.DAB[a * nb + b];
-      T4[q] = s;
-      atomicAdd(&L.sq[g], s * s);
-    }
+    for (int a0 = 0; a0 < na; a0 += 16)
+      for (int g0 = 0; g0 < ng; g0 += 16) {
+        double sq = 0.0;
+        for (int al = 0; al < PA; ++al) {
+          const double *Ya = Y + (long long)al * N;
+          const d4 h = tile_mm(
+              nb, [&](int r, int k) { return (a0 + r < na && k < nb) ? L.DAB[(a0 + r) * nb + k] : 0.0; },
+              [&](int k, int c) { return (k < nb && g0 + c < ng) ? Ya[k * ng + g0 + c] : 0.0; });
+          for (int e = 0; e < 4; ++e) {
+            const int a = a0 + kk + 4 * e, g = g0 + l16;
+            if (a < na && g < ng) {
+              T4[((long long)al * na + a) * ng + g] = h[e];
+              sq += h[e] * h[e];
+            }
+          }
+        }
+        nm += (unsigned long long)PA * ((nb + 3) >> 2);
+        sq += __shfl_xor(sq, 16);
+        sq += __shfl_xor(sq, 32);
+        t4max = fmax(t4max, wave_max(sq));
+      }
   }
-  // T3[al*na+a][b] = sum_g Y[al][b][g] D_AG[a][g]
-  if (okAG) {
+  // T3[(al,a)][b] = sum_g D_AG[a][g] Y[al][b][g]
+  double t3max = 0.0;
+  const int dAG = L.g_dAG[j];
+  if (dAG >= 0 && P.keepD[dAG]) {
+    const double *DAG = P.Dbuf + L.g_dAGoff[j];
     double *T3 = slot + L.a_t3[jj];
-    for (int q = tid; q < PA * na * nb; q += NT) {
-      const int al = q / (na * nb), a = (q / nb) % na, b = q % nb;
-      double s = 0;
-      for (int g = 0; g < ng; ++g) s += Y[(long long)al * N + b * ng + g] * L.DAG[a * ng + g];
-      T3[q] = s;
-      atomicAdd(&L.sq[MAXN + b], s * s);
-    }
+    for (int a0 = 0; a0 < na; a0 += 16)
+      for (int b0 = 0; b0 < nb; b0 += 16) {
+        double sq = 0.0;
+        for (int al = 0; al < PA; ++al) {
+          const double *Ya = Y + (long long)al * N;
+          const d4 h = tile_mm(
+              ng, [&](int r, int k) { return (a0 + r < na && k < ng) ? DAG[(a0 + r) * ng + k] : 0.0; },
+              [&](int k, int c) { return (k < ng && b0 + c < nb) ? Ya[(b0 + c) * ng + k] : 0.0; });
+          for (int e = 0; e < 4; ++e) {
+            const int a = a0 + kk + 4 * e, b = b0 + l16;
+            if (a < na && b < nb) {
+              T3[((long long)al * na + a) * nb + b] = h[e];
+              sq += h[e] * h[e];
+            }
+          }
+        }
+        nm += (unsigned long long)PA * ((ng + 3) >> 2);
+        sq += __shfl_xor(sq, 16);
+        sq += __shfl_xor(sq, 32);
+        t3max = fmax(t3max, wave_max(sq));
+      }
   }
-  __syncthreads();
-  if (tid == 0) {
-    double yb = 0, yg = 0, t3 = 0, t4 = 0;
-    for (int b = 0; b < nb; ++b) {
-      double s = 0;
-      for (int g = 0; g < ng; ++g) s += N1[(b * ng + g) * ng + g];
-      yb = fmax(yb, s);
-      t3 = fmax(t3, L.sq[MAXN + b]);
-    }
-    for (int g = 0; g < ng; ++g) {
-      double s = 0;
-      for (int b = 0; b < nb; ++b) s += M2[(g * nb + b) * nb + b];
-      yg = fmax(yg, s);
-      t4 = fmax(t4, L.sq[g]);
-    }
-    L.a_Yb[jj] = sqrt(yb);
-    L.a_Yg[jj] = sqrt(yg);
-    L.a_T3n[jj] = sqrt(t3);
-    L.a_T4n[jj] = sqrt(t4);
+  // N1[b][g][g'] = sum_al Y[al][b][g] Y[al][b][g'];  Yb^2 = max_b trace N1[b]
+  double *N1 = slot + L.a_n1[jj];
+  double ybmax = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    double tr = 0.0;
+    for (int g0 = 0; g0 < ng; g0 += 16)
+      for (int h0 = 0; h0 < ng; h0 += 16) {
+        const d4 h = tile_mm(
+            PA, [&](int r, int k) { return (g0 + r < ng && k < PA) ? Y[(long long)k * N + b * ng + g0 + r] : 0.0; },
+            [&](int k, int c) { return (k < PA && h0 + c < ng) ? Y[(long long)k * N + b * ng + h0 + c] : 0.0; });
+        for (int e = 0; e < 4; ++e) {
+          const int g = g0 + kk + 4 * e, g2 = h0 + l16;
+          if (g < ng && g2 < ng) {
+            N1[((long long)b * ng + g) * ng + g2] = h[e];
+            if (g == g2) tr += h[e];
+          }
+        }
+      }
+    ybmax = fmax(ybmax, wave_sum(tr));
   }
-  __syncthreads();
+  // M2[g][b][b'] = sum_al Y[al][b][g] Y[al][b'][g];  Yg^2 = max_g trace M2[g]
+  double *M2 = slot + L.a_m2[jj];
+  double ygmax = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    double tr = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 16)
+      for (int c0 = 0; c0 < nb; c0 += 16) {
+        const d4 h = tile_mm(
+            PA, [&](int r, int k) { return (b0 + r < nb && k < PA) ? Y[(long long)k * N + (b0 + r) * ng + g] : 0.0; },
+            [&](int k, int c) { return (k < PA && c0 + c < nb) ? Y[(long long)k * N + (c0 + c) * ng + g] : 0.0; });
+        for (int e = 0; e < 4; ++e) {
+          const int b = b0 + kk + 4 * e, b2 = c0 + l16;
+          if (b < nb && b2 < nb) {
+            M2[((long long)g * nb + b) * nb + b2] = h[e];
+            if (b == b2) tr += h[e];
+          }
+        }
+      }
+    ygmax = fmax(ygmax, wave_sum(tr));
+  }
+  const int tn = ((ng + 15) >> 4) * ((ng + 15) >> 4) * nb + ((nb + 15) >> 4) * ((nb + 15) >> 4) * ng;
+  nm += (unsigned long long)tn * ((PA + 3) >> 2);
+  if (lane == 0) {
+    L.a_Yb[jj] = sqrt(ybmax);
+    L.a_Yg[jj] = sqrt(ygmax);
+    L.a_T3n[jj] = sqrt(t3max);
+    L.a_T4n[jj] = sqrt(t4max);
+    atomicAdd(&L.cnt[kCntMfmaY], nm);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
 // masks: stages 2 and 3 for the stage-1 survivors of alive G's
-__device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, uint8_t *mask, double *E2) {
-  const int tid = threadIdx.x;
-  const int nb = L.nb;
+__device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, uint8_t *mask, double *E2,
+                            double *wreg) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
+  const int nb = L.nb, nF = L.nF, nGa = L.nGa, nG = L.nG;
   const double eps = P.eps_mat;
   const bool use2 = P.stages & kCs2, use3 = P.stages & kCs3;
-  // E2_i = D_FB^T D_FB  [b][b']
-  for (int q = tid; q < L.nF * nb * nb; q += NT) {
-    const int i = q / (nb * nb), b = (q / nb) % nb, b2 = q % nb;
+  unsigned long long c2[4] = {0, 0, 0, 0}, c3[4] = {0, 0, 0, 0}, nm = 0;
+  // E2_i = D_FB^T D_FB  [b][b']  (one wave per F)
+  for (int i = wave; i < nF; i += NW) {
+    double *E = E2 + (long long)i * nb * nb;
     const int dFB = L.f_dFB[i];
-    double s = 0;
-    if (dFB >= 0) {
-      const double *D = P.Dbuf + L.f_dFBoff[i];
-      const int nf = L.f_n[i];
-      for (int f = 0; f < nf; ++f) s += D[f * nb + b] * D[f * nb + b2];
-    }
-    E2[q] = s;
+    const int nf = L.f_n[i];
+    if (dFB < 0) continue;
+    const double *D = P.Dbuf + L.f_dFBoff[i];
+    for (int b0 = 0; b0 < nb; b0 += 16)
+      for (int c0 = 0; c0 < nb; c0 += 16) {
+        const d4 h = tile_mm(
+            nf, [&](int r, int k) { return (b0 + r < nb && k < nf) ? D[k * nb + b0 + r] : 0.0; },
+            [&](int k, int c) { return (k < nf && c0 + c < nb) ? D[k * nb + c0 + c] : 0.0; });
+        for (int e = 0; e < 4; ++e) {
+          const int b = b0 + kk + 4 * e, b2 = c0 + l16;
+          if (b < nb && b2 < nb) E[b * nb + b2] = h[e];
+        }
+        nm += (nf + 3) >> 2;
+      }
   }
-  __syncthreads();
-  unsigned long long c2[4] = {0, 0, 0, 0}, c3[4] = {0, 0, 0, 0};
-  for (int p = tid; p < L.nF * L.nGa; p += NT) {
-    const int i = p / L.nGa, jj = p - i * L.nGa;
+  // stage 2 for every term, stage 3 for terms 3 and 4; terms 1 and 2 marked pending
+  for (int p = tid; p < nF * nGa; p += NT) {
+    const int i = p / nGa, jj = p - i * nGa;
     const int j = L.a_j[jj];
-    const int q = i * L.nG + j;
+    const int q = i * nG + j;
     uint8_t bits = mask[q];
     if (!(bits & 15)) continue;
-    const int ng = L.g_n[j];
-    (void)ng;
-    // term 1 (stage 3 is evaluated below, one wave per unit)
     if (bits & kT1) {
-      const int d = dfg[q];
-      const bool keep = !use2 || L.f_gA[i] * L.a_Yb[jj] * P.gD[d] > eps;
-      if (keep) {
+      if (!use2 || L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]] > eps) {
         ++c2[0];
         if (use3)
           bits |= kPend1;
@@ -298,29 +388,17 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
         bits &= ~kT1;
       }
     }
-    // term 2
     if (bits & kT2) {
-      const int d = L.f_dFB[i];
-      bool keep = !use2 || L.f_gA[i] * L.a_Yg[jj] * P.gD[d] > eps;
-      if (keep) {
+      if (!use2 || L.f_gA[i] * L.a_Yg[jj] * P.gD[L.f_dFB[i]] > eps) {
         ++c2[1];
-        if (use3) {
-          // ||T2[:,:,g]||^2 = sum_{b,b'} (D^T D)[b][b'] M2[g][b][b'],  D = D_FB [f][b]
-          const double *M2 = slot + L.a_m2[jj];
-          const double *E = E2 + i * nb * nb;
-          double tmax = 0;
-          for (int g = 0; g < ng; ++g) {
-            double s = 0;
-            for (int b = 0; b < nb * nb; ++b) s += E[b] * M2[g * nb * nb + b];
-            tmax = fmax(tmax, s);
-          }
-          keep = L.f_nA[i] * sqrt(fmax(tmax, 0.0)) > eps;
-        }
-        if (keep) ++c3[1];
+        if (use3)
+          bits |= kPend2;
+        else
+          ++c3[1];
+      } else {
+        bits &= ~kT2;
       }
-      if (!keep) bits &= ~kT2;
     }
-    // term 3
     if (bits & kT3) {
       bool keep = !use2 || L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]] > eps;
       if (keep) {
@@ -330,7 +408,6 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       }
       if (!keep) bits &= ~kT3;
     }
-    // term 4
     if (bits & kT4) {
       bool keep = !use2 || L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB] > eps;
       if (keep) {
@@ -343,39 +420,104 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
     mask[q] = bits;
   }
   __syncthreads();
-  // term 1, stage 3:  ||T1[:,:,b]||^2 = sum_{g,g'} (D^T D)[g][g'] N1[b][g][g'],  D = D_FG [f][g]
-  // (the Gram form of ||(V C) D||, so T1 itself is never formed for a dropped unit)
-  {
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int p = wave; p < L.nF * L.nGa; p += NW) {
-      const int i = p / L.nGa, jj = p - i * L.nGa;
-      const int j = L.a_j[jj];
-      const int q = i * L.nG + j;
-      const uint8_t bits = mask[q];
-      if (!(bits & kPend1)) continue;
-      const int ng = L.g_n[j], nf = L.f_n[i];
-      const double *D = P.Dbuf + P.d_off[dfg[q]];
+  if (use3) {
+    // term 2, stage 3: ||T2[:,:,g]||^2 = <E2_F, M2_G[g]> for every (F, G): one 16-F x 16-g tile
+    // per (F tile, G) over K = nb*nb
+    const int nft = (nF + 15) >> 4;
+    for (int t = wave; t < nft * nGa; t += NW) {
+      const int it = t / nGa, jj = t - it * nGa;
+      const int j = L.a_j[jj], ng = L.g_n[j];
+      const int i = (it << 4) + l16;
+      const bool pend = i < nF && (mask[i * nG + j] & kPend2);
+      if (!__any(pend)) continue;
+      const double *M2 = slot + L.a_m2[jj];
+      const int K = nb * nb;
+      double smax[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int g0 = 0; g0 < ng; g0 += 16) {
+        const d4 h = tile_mm(
+            K, [&](int r, int k) { return ((it << 4) + r < nF && k < K) ? E2[(long long)((it << 4) + r) * K + k] : 0.0; },
+            [&](int k, int c) { return (k < K && g0 + c < ng) ? M2[(long long)(g0 + c) * K + k] : 0.0; });
+        nm += (K + 3) >> 2;
+        for (int e = 0; e < 4; ++e) smax[e] = fmax(smax[e], (g0 + l16 < ng) ? h[e] : 0.0);
+      }
+      for (int e = 0; e < 4; ++e) {
+        double v = smax[e];
+        for (int o = 1; o < 16; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+        const int ii = (it << 4) + kk + 4 * e;
+        if (l16 == 0 && ii < nF) {
+          const int q = ii * nG + j;
+          const uint8_t bits = mask[q];
+          if (bits & kPend2) {
+            const bool keep = L.f_nA[ii] * sqrt(fmax(v, 0.0)) > eps;
+            mask[q] = keep ? (uint8_t)(bits & ~kPend2) : (uint8_t)(bits & ~(kPend2 | kT2));
+            if (keep) ++c3[1];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // term 1, stage 3: ||T1[:,:,b]||^2 = <D_FG^T D_FG, N1_G[b]>; per G, 16 pending F's at a time:
+    // E1_F = D_FG^T D_FG into the wave's scratch, then one 16-F x 16-b tile over K = ng*ng
+    double *E1 = wreg;  // [16][MAXN*MAXN]
+    for (int jj = wave; jj < nGa; jj += NW) {
+      const int j = L.a_j[jj], ng = L.g_n[j];
+      const int K = ng * ng;
       const double *N1 = slot + L.a_n1[jj];
-      double e[16];
-      int ne = 0;
-      for (int x = lane; x < ng * ng && ne < 16; x += 64, ++ne) {
-        const int g = x / ng, g2 = x - g * ng;
-        double s = 0;
-        for (int f = 0; f < nf; ++f) s += D[f * ng + g] * D[f * ng + g2];
-        e[ne] = s;
-      }
-      double tmax = 0;
-      for (int b = 0; b < nb; ++b) {
-        double s = 0;
-        int k = 0;
-        for (int x = lane; x < ng * ng && k < 16; x += 64, ++k) s += e[k] * N1[b * ng * ng + x];
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        tmax = fmax(tmax, s);
-      }
-      const bool keep = L.f_nA[i] * sqrt(fmax(tmax, 0.0)) > eps;
-      if (lane == 0) {
-        mask[q] = keep ? (uint8_t)(bits & ~kPend1) : (uint8_t)(bits & ~(kPend1 | kT1));
-        if (keep) ++c3[0];
+      int ib = 0;
+      for (;;) {
+        // next batch of up to 16 pending F's
+        int fl[16];
+        int nbat = 0;
+        while (nbat < 16 && ib < nF) {
+          const int i = ib + lane;
+          const bool pend = i < nF && (mask[i * nG + j] & kPend1);
+          unsigned long long bm = __ballot(pend);
+          while (bm && nbat < 16) {
+            const int o = __builtin_ctzll(bm);
+            bm &= bm - 1;
+            fl[nbat++] = ib + o;
+          }
+          ib = bm ? ib + __builtin_ctzll(bm) : ib + 64;
+        }
+        if (nbat == 0) break;
+        for (int r = 0; r < nbat; ++r) {
+          const int i = fl[r], nf = L.f_n[i];
+          const double *D = P.Dbuf + P.d_off[dfg[i * nG + j]];
+          for (int g0 = 0; g0 < ng; g0 += 16)
+            for (int h0 = 0; h0 < ng; h0 += 16) {
+              const d4 h = tile_mm(
+                  nf, [&](int rr, int k) { return (g0 + rr < ng && k < nf) ? D[k * ng + g0 + rr] : 0.0; },
+                  [&](int k, int c) { return (k < nf && h0 + c < ng) ? D[k * ng + h0 + c] : 0.0; });
+              nm += (nf + 3) >> 2;
+              for (int e = 0; e < 4; ++e) {
+                const int g = g0 + kk + 4 * e, g2 = h0 + l16;
+                if (g < ng && g2 < ng) E1[r * MAXN * MAXN + g * ng + g2] = h[e];
+              }
+            }
+        }
+        __threadfence_block();
+        double smax[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b0 = 0; b0 < nb; b0 += 16) {
+          const d4 h = tile_mm(
+              K, [&](int r, int k) { return (r < nbat && k < K) ? E1[r * MAXN * MAXN + k] : 0.0; },
+              [&](int k, int c) { return (k < K && b0 + c < nb) ? N1[(long long)(b0 + c) * K + k] : 0.0; });
+          nm += (K + 3) >> 2;
+          for (int e = 0; e < 4; ++e) smax[e] = fmax(smax[e], (b0 + l16 < nb) ? h[e] : 0.0);
+        }
+        for (int e = 0; e < 4; ++e) {
+          double v = smax[e];
+          for (int o = 1; o < 16; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+          const int r = kk + 4 * e;
+          if (l16 == 0 && r < nbat) {
+            const int i = fl[r];
+            const int q = i * nG + j;
+            const uint8_t bits = mask[q];
+            const bool keep = L.f_nA[i] * sqrt(fmax(v, 0.0)) > eps;
+            mask[q] = keep ? (uint8_t)(bits & ~kPend1) : (uint8_t)(bits & ~(kPend1 | kT1));
+            if (keep) ++c3[0];
+          }
+        }
+        __threadfence_block();
       }
     }
   }
@@ -383,6 +525,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
     if (c2[t]) atomicAdd(&L.cnt[kCntKept + 4 + t], c2[t]);
     if (c3[t]) atomicAdd(&L.cnt[kCntKept + 8 + t], c3[t]);
   }
+  if (lane == 0 && nm) atomicAdd(&L.cnt[kCntMfmaY], nm);
 }
 
 __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
@@ -735,6 +878,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     const long long t_start = wall_clock64();
     const Item it = P.items[item];
     if (tid < kCntN) L.cnt[tid] = 0;
+    if (tid < 2) L.flops[tid] = 0.0;
     if (tid == 0) {
       L.A = it.A;
       L.B = it.B;
@@ -860,9 +1004,18 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       L.scratch_top = (int)off;
     }
     __syncthreads();
-    for (int jj = 0; jj < L.nGa; ++jj) phase_gside_one(P, L, slot, jj);
+    {
+      // V_AB in LDS when it fits in the accumulator region (not in use in this phase)
+      const bool vlds = L.PA * L.PB <= NW * kp.acc_doubles;
+      const double *Vsrc = vlds ? accw : P.Vbuf + L.voff;
+      if (vlds)
+        for (int q = tid; q < L.PA * L.PB; q += NT) accw[q] = P.Vbuf[L.voff + q];
+      __syncthreads();
+      for (int jj = tid >> 6; jj < L.nGa; jj += NW) gside_wave(P, L, slot, jj, Vsrc);
+      __syncthreads();
+    }
     tick(1);
-    phase_masks(P, L, slot, dfg, mask, E2);
+    phase_masks(P, L, slot, dfg, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
       int lo = 0, hi = L.nF - 1;
@@ -886,6 +1039,33 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       }
       col2jj[c] = (short)lo;
     }
+    // FLOP accounting of the item (both counts exclude padding and screened-out work):
+    //   paper: Algorithm 3 per kept unit -- T_t and Htilde_t for terms 1, 2; Htilde_t for terms
+    //          3, 4 (T3, T4 once per G) -- plus Y, T3, T4 once per alive G
+    //   alg:   this kernel -- one C.D or C^T.T product per kept unit, plus Y, T3, T4, the two
+    //          Gram matrices and the two Y contractions once per alive G
+    {
+      double fp = 0.0, fa = 0.0;
+      const double PA = L.PA, na = L.na, nb = L.nb;
+      for (int p = tid; p < L.nF * L.nGa; p += NT) {
+        const int i = p / L.nGa, jj = p - i * L.nGa;
+        const int j = L.a_j[jj];
+        const uint8_t bits = mask[i * L.nG + j];
+        const double nf = L.f_n[i], ng = L.g_n[j];
+        if (bits & kT1) { fp += 2 * PA * nf * nb * ng + 2 * na * PA * nf * nb; fa += 2 * PA * na * nf * ng; }
+        if (bits & kT2) { fp += 2 * PA * nf * ng * nb + 2 * na * PA * nf * ng; fa += 2 * PA * na * nf * nb; }
+        if (bits & kT3) { fp += 2 * nf * PA * na * nb; fa += 2 * nf * PA * na * nb; }
+        if (bits & kT4) { fp += 2 * nf * PA * na * ng; fa += 2 * nf * PA * na * ng; }
+      }
+      for (int jj = tid; jj < L.nGa; jj += NT) {
+        const double ng = L.g_n[L.a_j[jj]];
+        const double g = 2 * PA * L.PB * nb * ng + 2 * 2 * PA * na * nb * ng;
+        fp += g;
+        fa += g + 2 * PA * (nb * ng * ng + ng * nb * nb) + 2 * 2 * PA * na * nb * ng;
+      }
+      if (fp != 0.0) atomicAdd(&L.flops[0], fp);
+      if (fa != 0.0) atomicAdd(&L.flops[1], fa);
+    }
     __syncthreads();
     tick(2);
     if (L.nGa > 0) {
@@ -905,6 +1085,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
         if (v != 0.0) atomicAdd(P.Sbuf + P.d_off[L.dAB] + q, -v);
       }
     if (tid < kCntN && L.cnt[tid]) atomicAdd(&P.counters[tid], L.cnt[tid]);
+    if (tid < 2 && L.flops[tid] != 0.0) atomicAdd(&P.flops[tid], L.flops[tid]);
     if (tid < 4) P.item_units[item * 4 + tid] = (int)L.cnt[kCntKept + 8 + tid];
     if (tid == 0) P.item_cycles[item] = wall_clock64() - t_start;
     __syncthreads();
@@ -1141,9 +1322,10 @@ __global__ void k_zero(double *__restrict__ p, long long n) {
     p[q] = 0.0;
 }
 
-__global__ void k_reset(unsigned int *ticket, unsigned long long *counters) {
+__global__ void k_reset(unsigned int *ticket, unsigned long long *counters, double *flops) {
   if (threadIdx.x == 0) *ticket = 0;
   if (threadIdx.x < kCntN) counters[threadIdx.x] = 0;
+  if (threadIdx.x < 2) flops[threadIdx.x] = 0.0;
 }
 
 // energy: per-workgroup double-double partial sums of <D, Sigma>
@@ -1239,8 +1421,8 @@ hipError_t launch_zero(double *p, long long n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_zero, dim3(2048), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
-hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ticket, counters);
+hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, double *flops, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ticket, counters, flops);
   return hipGetLastError();
 }
 hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s) {

@@ -43,7 +43,7 @@ hipError_t launch_dprep(const double *Dbuf, const long long *d_off, const int *d
 hipError_t launch_zero(double *p, long long n, hipStream_t s);
 hipError_t launch_dmax(const double *gD, const uint8_t *keepD, const long long *dbase, double *gDmax, int n_cells,
                        hipStream_t s);
-hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, hipStream_t s);
+hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, double *flops, hipStream_t s);
 hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s);
 }  // namespace hfx
 
@@ -568,10 +568,12 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     return fail(HFX_ERR_UNSUPPORTED, "neighbour lists too long for the decode tables");
   const int64_t nfg = (int64_t)max_nbr * max_nbr;
   p->wave_off = (nfg + 1) / 2 + (nfg + 7) / 8 + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
-  p->wave_doubles = ((int64_t)p->rows_cap * 33 + (int64_t)max_p * max_n * 32 + 64 + 31) / 32 * 32;
+  p->wave_doubles = (std::max<int64_t>((int64_t)p->rows_cap * 33 + (int64_t)max_p * max_n * 32,
+                                       16 * (int64_t)main_maxn() * main_maxn()) +
+                     64 + 31) / 32 * 32;
   const int64_t slot = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
-  const int J = 16 / (2 * min_n) + 2;
-  p->acc_doubles = std::max(16 * main_maxn(), J * max_n * main_maxn());
+  (void)min_n;
+  p->acc_doubles = 16 * main_maxn();
   const size_t lds = main_static_lds() + (size_t)p->rows_cap + 2 * (size_t)p->cols_cap +
                      (size_t)main_nwaves() * p->acc_doubles * sizeof(double);
   if (lds > 160 * 1024)
@@ -590,17 +592,22 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   // ---- device memory
   DevPlan &P = p->dp;
   hfx_status st;
-  int32_t *d_nao, *d_nabf, *d_cellof, *d_localof, *d_cstart, *d_ccol, *d_cR, *d_crow, *d_vrow, *d_vcol, *d_qsrc;
-  long long *d_coff, *d_voff, *d_doff;
-  double *d_C, *d_CT, *d_V, *d_gV, *d_gD, *d_D, *d_S, *d_scr;
-  CNorm *d_cn;
-  int32_t *d_ptoff, *d_pstart, *d_pcount, *d_dsR, *d_dsid, *d_cellnat, *d_order, *d_drow, *d_dcol;
-  uint8_t *d_keepD;
-  Item *d_items;
-  unsigned int *d_ticket;
-  unsigned long long *d_cnt;
-  long long *d_icyc;
-  int *d_iunits;
+  int32_t *d_nao = nullptr, *d_nabf = nullptr, *d_cellof = nullptr, *d_localof = nullptr, *d_cstart = nullptr,
+          *d_ccol = nullptr, *d_cR = nullptr, *d_crow = nullptr, *d_vrow = nullptr, *d_vcol = nullptr,
+          *d_qsrc = nullptr;
+  long long *d_coff = nullptr, *d_voff = nullptr, *d_doff = nullptr;
+  double *d_C = nullptr, *d_CT = nullptr, *d_V = nullptr, *d_gV = nullptr, *d_gD = nullptr, *d_D = nullptr,
+         *d_S = nullptr, *d_scr = nullptr;
+  CNorm *d_cn = nullptr;
+  int32_t *d_ptoff = nullptr, *d_pstart = nullptr, *d_pcount = nullptr, *d_dsR = nullptr, *d_dsid = nullptr,
+          *d_cellnat = nullptr, *d_order = nullptr, *d_drow = nullptr, *d_dcol = nullptr;
+  uint8_t *d_keepD = nullptr;
+  Item *d_items = nullptr;
+  unsigned int *d_ticket = nullptr;
+  unsigned long long *d_cnt = nullptr;
+  double *d_flops = nullptr;
+  long long *d_icyc = nullptr;
+  int *d_iunits = nullptr;
   std::vector<int32_t> ord32(p->order.begin(), p->order.end());
   if ((st = p->upload(&d_nao, p->nao)) || (st = p->upload(&d_nabf, p->nabf)) ||
       (st = p->upload(&d_cellof, p->cell_of)) || (st = p->upload(&d_localof, p->local_of)) ||
@@ -617,7 +624,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       (st = p->dalloc(&d_S, (size_t)p->sbase[n_cells])) || (st = p->dalloc(&d_gD, (size_t)p->nD)) ||
       (st = p->dalloc(&d_keepD, (size_t)p->nD)) || (st = p->upload(&d_items, p->items)) ||
       (st = p->upload(&d_order, ord32)) || (st = p->dalloc(&d_ticket, 1)) || (st = p->dalloc(&d_cnt, kCntN)) ||
-      (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * 4)) ||
+      (st = p->dalloc(&d_flops, 2)) || (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * 4)) ||
       (st = p->dalloc(&d_scr, (size_t)p->n_slots * slot)) || (st = p->dalloc(&p->part, 2 * p->part_blocks)))
     return st;
   cstage.clear();
@@ -678,9 +685,19 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   P.max_n = max_n;
   P.ticket = d_ticket;
   P.counters = d_cnt;
+  P.flops = d_flops;
   P.item_cycles = d_icyc;
   P.item_units = d_iunits;
 
+  {
+    const void *must[] = {P.nao, P.nabf, P.cell_of, P.local_of, P.Cbuf, P.CTbuf, P.c_off, P.c_col, P.c_R, P.c_norm,
+                          P.c_start, P.Vbuf, P.v_off, P.gV, P.ptab_off, P.pstart, P.pcount, P.dsort_R, P.dsort_id,
+                          P.cell_natoms, P.d_off, P.Dbuf, P.gD, P.keepD, P.gDmax, P.Sbuf, P.items, P.order,
+                          P.scratch, P.ticket, P.counters, P.flops, P.item_cycles, P.item_units, p->part,
+                          p->d_row_dev, p->d_col_dev, p->dbase_dev};
+    for (const void *q : must)
+      if (!q) return fail(HFX_ERR_OOM, "internal: a device buffer of the plan was not allocated");
+  }
   // ---- plan-time kernels: C norms, CS-ERI factors, V norms
   HIPCHK(p, launch_cnorm(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_cn, p->stream));
   HIPCHK(p, launch_ctrans(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_CT, p->stream));
@@ -762,7 +779,7 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
                          const_cast<uint8_t *>(P.keepD), p->stream));
   HIPCHK(p, launch_dmax(P.gD, P.keepD, p->dbase_dev, p->gDmax_dev, p->n_cells, p->stream));
   HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
-  HIPCHK(p, launch_reset(P.ticket, P.counters, p->stream));
+  HIPCHK(p, launch_reset(P.ticket, P.counters, P.flops, p->stream));
   HIPCHK(p, hipEventRecord(p->ev1, p->stream));
   if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->acc_doubles, p->wave_off, p->wave_doubles,
                                           p->stream));
@@ -783,9 +800,14 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
       for (int t = 0; t < 4; ++t) stats->kept[s][t] = (int64_t)cnt[kCntKept + 4 * s + t];
     stats->items = p->n_items;
     stats->g_alive = (int64_t)cnt[kCntG];
-    const double mf = 2048.0 * (double)(cnt[kCntMfmaR] + cnt[kCntMfmaL] + cnt[kCntMfmaY]);
-    stats->flops_tier[0] = mf;
-    stats->flops_contract = mf;
+    double fl[2];
+    HIPCHK(p, hipMemcpy(fl, P.flops, sizeof(fl), hipMemcpyDeviceToHost));
+    stats->flops_paper = fl[0];
+    stats->flops_contract = fl[1];
+    stats->flops_tier[0] = fl[1];
+    stats->mfma_flops[0] = 2048.0 * (double)cnt[kCntMfmaY];
+    stats->mfma_flops[1] = 2048.0 * (double)cnt[kCntMfmaR];
+    stats->mfma_flops[2] = 2048.0 * (double)cnt[kCntMfmaL];
     float ms0 = 0, ms1 = 0;
     HIPCHK(p, hipEventElapsedTime(&ms0, p->ev0, p->ev2));
     HIPCHK(p, hipEventElapsedTime(&ms1, p->ev1, p->ev2));
