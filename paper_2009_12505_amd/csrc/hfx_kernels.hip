@@ -32,7 +32,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int NT = 512;
 constexpr int NW = NT / 64;
-constexpr int MAXNB = 256;
+constexpr int MAXNB = 160;
 constexpr int MAXN = 32;
 constexpr int kTileWords = 8;  // column-tile bitmask words of GEMM-R (up to 512 tiles)
 
@@ -97,7 +97,13 @@ struct ItemLds {
   double DAB[MAXN * MAXN];
   double DAG[MAXN * MAXN];
   double sq[2 * MAXN];
-  double tile[NW][256];
+  // GEMM block bookkeeping
+  unsigned blk_act;
+  int t1any, kc, nsel;
+  unsigned long long t2any;
+  int fpos[MAXNB];
+  short fsel[MAXNB];
+  int fsrow[MAXNB + 1];
   unsigned long long cnt[kCntN];
   double flops[2];
   int scratch_top;
@@ -105,9 +111,10 @@ struct ItemLds {
 
 struct KParams {
   int rows_cap, cols_cap;  // sizes of the row/col decode tables (bytes) in dynamic LDS
-  int acc_doubles;         // per-wave accumulator (doubles) in dynamic LDS
+  int ld3;                 // row stride of the per-wave term-3 accumulators in dynamic LDS
   long long wave_off;      // offset (doubles) of the per-wave scratch regions in a slot
   long long wave_doubles;  // size of one per-wave region
+  long long wg_off;        // offset (doubles) of the workgroup region (GEMM-L panel, P block)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -533,136 +540,168 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// GEMM-R: terms 3 and 4.  Rows (F,f), K = (alpha,a), columns (G, [g | b]).
-// A wave owns a 16-row strip and walks its active 16-column tiles four at a time, so
-// each A fragment feeds four MFMAs; loads of step k+1 are issued before the MFMAs of k.
+// Workgroup block product: a 128-row x 64-column output block, K streamed through two LDS
+// stages in chunks of 16.  Each thread fetches four A elements (row tid&127) and two B
+// elements (column tid&63) of the next chunk into registers while the MFMAs of the current
+// chunk run, then stores them into the other stage; wave w owns row tile w and column
+// tiles 0..3 (act: which of the four to compute).
+// a_at(k) / b_at(k) return this thread's A / B element at k (0 outside the operands).
+constexpr int BM = 128, BN = 64, BK = 16;
+
+template <class AAt, class BAt>
+__device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned act, double *As, double *Bs,
+                                            d4 (&acc)[4]) {
+  // As, Bs: two stages each ([2][BK][BM], [2][BK][BN]); one barrier per chunk
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
+  const int ar = tid & (BM - 1), akq = (tid >> 7) << 2;
+  const int bc = tid & (BN - 1), bk = tid >> 6;
+  double ra[4], rb[2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0;
+    rb[0] = k0 + bk < K ? b_at(k0 + bk) : 0.0;
+    rb[1] = k0 + bk + 8 < K ? b_at(k0 + bk + 8) : 0.0;
+  };
+  auto stash = [&](int st) {
+    double *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = ra[s];
+    b[bk * BN + bc] = rb[0];
+    b[(bk + 8) * BN + bc] = rb[1];
+  };
+  __syncthreads();  // the previous user of the stages is done
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int st = 0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) fetch(k0 + BK);
+    if (act) {
+      const double *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+#pragma unroll
+      for (int s = 0; s < BK / 4; ++s) {
+        const int kr = 4 * s + kk;
+        const double av = a[kr * BM + wave * 16 + l16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (act & (1u << v)) acc[v] = mfma64(av, b[kr * BN + v * 16 + l16], acc[v]);
+      }
+    }
+    if (more) stash(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+}
+
+// which of the four 16-column tiles of [c_lo, c_lo+64) hold a half (g or b) of some alive G
+// whose bit for F_i is set: bits_g for the g-half, bits_b for the b-half
+__device__ __forceinline__ bool tile_has(const ItemLds &L, const uint8_t *mask, const short *col2jj, int i, int c_lo,
+                                         int c_hi, uint8_t bits_g, uint8_t bits_b) {
+  if (c_lo >= c_hi) return false;
+  const int jj0 = col2jj[c_lo], jj1 = col2jj[c_hi - 1];
+  for (int jj = jj0; jj <= jj1; ++jj) {
+    const int j = L.a_j[jj];
+    const int g0 = L.a_col0[jj], gb = g0 + L.g_n[j], g1 = L.a_col0[jj + 1];
+    const uint8_t bits = mask[i * L.nG + j];
+    if ((bits & bits_g) && max(c_lo, g0) < min(c_hi, gb)) return true;
+    if ((bits & bits_b) && max(c_lo, gb) < min(c_hi, g1)) return true;
+  }
+  return false;
+}
+
+// ---------------------------------------------------------------------------------------------
+// GEMM-R: terms 3 and 4.  Rows (F,f), K = (alpha,a), columns (G, [g | b]):
+//   out[(F,f)][(G,g)] = sum_{al,a} C_AF[al][a][f] T4_G[al][a][g]  -> Sigma(F,G)  (term 4)
+//   out[(F,f)][(G,b)] = sum_{al,a} C_AF[al][a][f] T3_G[al][a][b]  -> summed over G into Sigma(F,B)
+// 128 x 64 blocks in row-block-major order; a block whose 32 tiles hold no kept unit is skipped.
 __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
-                             const uint8_t *row2i, const short *col2jj, double *accw, int acc_doubles) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+                             const uint8_t *row2i, const short *col2jj, double *As, double *Bs, double *acc3,
+                             int ld3) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int K = L.PA * L.na, nb = L.nb;
-  const int mt = (L.MR + 15) >> 4, nt = (L.NR + 15) >> 4;
-  double *acc3 = accw + wave * acc_doubles;  // [16 rows][MAXN]
+  const int nrb = (L.MR + BM - 1) / BM, ncb = (L.NR + BN - 1) / BN;
   unsigned long long nmfma = 0;
-  const int kk = lane >> 4;
-  for (int rt = wave; rt < mt; rt += NW) {
-    for (int q = lane; q < 16 * MAXN; q += 64) acc3[q] = 0.0;
+  for (int rb = 0; rb < nrb; ++rb) {
+    for (int q = lane; q < 16 * ld3; q += 64) acc3[q] = 0.0;
     bool any3 = false;
-    const int ra = (rt << 4) + (lane & 15);
-    const bool rowok = ra < L.MR;
-    const int ia = rowok ? row2i[ra] : 0;
-    const int fa = rowok ? ra - L.f_row0[ia] : 0;
-    const double *Arow = P.Cbuf + L.f_coff[ia] + fa;
-    const int nfa = L.f_n[ia];
-    // active column tiles of this strip (exact test over each tile's 256 elements)
-    unsigned long long act[kTileWords];
-    for (int w = 0; w < kTileWords; ++w) act[w] = 0;
-    for (int ct = 0; ct < nt; ++ct) {
-      bool need = false;
-      if (rowok) {
-        for (int e = 0; e < 4; ++e) {
-          const int c = (ct << 4) + (kk << 2) + e;
-          if (c < L.NR) {
-            const int jj = col2jj[c], j = L.a_j[jj];
-            const int cc = c - L.a_col0[jj];
-            const uint8_t bits = mask[ia * L.nG + j];
-            need |= (cc < L.g_n[j]) ? (bits & kT4) != 0 : (bits & kT3) != 0;
-          }
+    // this thread's A row
+    const int r = rb * BM + (tid & (BM - 1));
+    const bool rok = r < L.MR;
+    const int ia = rok ? row2i[r] : 0;
+    const double *Ab = P.Cbuf + L.f_coff[ia] + (rok ? r - L.f_row0[ia] : 0);
+    const int As_ = L.f_n[ia];
+    for (int cb = 0; cb < ncb; ++cb) {
+      if (tid == 0) L.blk_act = 0;
+      __syncthreads();
+      {
+        const int sidx = tid >> 4, wr = sidx >> 2, ct = sidx & 3;
+        const int rr = rb * BM + wr * 16 + (tid & 15);
+        if (rr < L.MR) {
+          const int c_lo = cb * BN + ct * 16;
+          if (tile_has(L, mask, col2jj, row2i[rr], c_lo, min(c_lo + 16, L.NR), kT4, kT3))
+            atomicOr(&L.blk_act, 1u << sidx);
         }
       }
-      if (__any(need)) act[ct >> 6] |= 1ull << (ct & 63);
-    }
-    int wi = 0;
-    unsigned long long m = act[0];
-    for (;;) {
-      int tiles[4] = {0, 0, 0, 0};
-      int n4 = 0;
-      while (n4 < 4) {
-        while (m == 0 && wi + 1 < kTileWords) m = act[++wi];
-        if (m == 0) break;
-        tiles[n4++] = (wi << 6) + __builtin_ctzll(m);
-        m &= m - 1;
-      }
-      if (n4 == 0) break;
-      const double *Bc[4];
-      int ldb[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Bc[v] = nullptr;
-        ldb[v] = 0;
-        const int cb = (tiles[v] << 4) + (lane & 15);
-        if (v < n4 && cb < L.NR) {
-          const int jj = col2jj[cb], j = L.a_j[jj];
-          const int cc = cb - L.a_col0[jj], ng = L.g_n[j];
-          if (cc < ng) {
-            Bc[v] = slot + L.a_t4[jj] + cc;
-            ldb[v] = ng;
-          } else {
-            Bc[v] = slot + L.a_t3[jj] + (cc - ng);
-            ldb[v] = nb;
-          }
+      __syncthreads();
+      const unsigned act_all = L.blk_act;
+      if (!act_all) continue;
+      const unsigned act = (act_all >> (4 * wave)) & 15u;
+      const int c = cb * BN + (tid & (BN - 1));
+      const bool cok = c < L.NR;
+      const double *Bb = slot;
+      int Bstr = 0;
+      if (cok) {
+        const int jj = col2jj[c], j = L.a_j[jj];
+        const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+        if (cc < ng) {
+          Bb = slot + L.a_t4[jj] + cc;
+          Bstr = ng;
+        } else {
+          Bb = slot + L.a_t3[jj] + (cc - ng);
+          Bstr = nb;
         }
       }
       d4 acc[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
-      double a_c = (rowok && kk < K) ? Arow[(long long)kk * nfa] : 0.0;
-      double b_c[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b_c[v] = (Bc[v] && kk < K) ? Bc[v][(long long)kk * ldb[v]] : 0.0;
-      for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + 4 + kk;
-        double a_n = 0.0, b_n[4] = {0.0, 0.0, 0.0, 0.0};
-        if (k < K) {
-          if (rowok) a_n = Arow[(long long)k * nfa];
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (Bc[v]) b_n[v] = Bc[v][(long long)k * ldb[v]];
-        }
-        acc[0] = mfma64(a_c, b_c[0], acc[0]);
-        if (n4 > 1) acc[1] = mfma64(a_c, b_c[1], acc[1]);
-        if (n4 > 2) acc[2] = mfma64(a_c, b_c[2], acc[2]);
-        if (n4 > 3) acc[3] = mfma64(a_c, b_c[3], acc[3]);
-        a_c = a_n;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) b_c[v] = b_n[v];
-      }
-      nmfma += (unsigned long long)n4 * ((K + 3) >> 2);
-      // epilogue: term 4 straight to Sigma(F,G), term 3 into the strip accumulator
+      wg_block_mm(
+          K, [&](int k) { return rok ? Ab[(long long)k * As_] : 0.0; },
+          [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, As, Bs, acc);
+      nmfma += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
+      // epilogue of this wave's tiles
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (v >= n4) break;
-        const int c = (tiles[v] << 4) + (lane & 15);
-        if (c >= L.NR) continue;
-        const int jj = col2jj[c], j = L.a_j[jj];
-        const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+        if (!(act & (1u << v))) continue;
+        const int cc0 = cb * BN + v * 16 + l16;
+        if (cc0 >= L.NR) continue;
+        const int jj = col2jj[cc0], j = L.a_j[jj];
+        const int cc = cc0 - L.a_col0[jj], ng = L.g_n[j];
         for (int e = 0; e < 4; ++e) {
-          const int rl = (lane >> 4) + 4 * e;
-          const int r = (rt << 4) + rl;
-          if (r >= L.MR) continue;
-          const int i = row2i[r], f = r - L.f_row0[i];
+          const int rl = kk + 4 * e;
+          const int rr = rb * BM + wave * 16 + rl;
+          if (rr >= L.MR) continue;
+          const int i = row2i[rr], f = rr - L.f_row0[i];
           const uint8_t bits = mask[i * L.nG + j];
           const double w = unit_weight(L, i, j);
           if (cc < ng) {
-            if (bits & kT4) {
-              const int d = dfg[i * L.nG + j];
-              atomicAdd(P.Sbuf + P.d_off[d] + f * ng + cc, -w * acc[v][e]);
-            }
+            if (bits & kT4) atomicAdd(P.Sbuf + P.d_off[dfg[i * L.nG + j]] + f * ng + cc, -w * acc[v][e]);
           } else if (bits & kT3) {
-            atomicAdd(&acc3[rl * MAXN + (cc - ng)], -w * acc[v][e]);
+            atomicAdd(&acc3[rl * ld3 + (cc - ng)], -w * acc[v][e]);
             any3 = true;
           }
         }
       }
     }
-    // flush term 3: Sigma(F,B)[f][b]
+    // flush term 3 of this wave's 16 rows: Sigma(F,B)[f][b]
     if (__any(any3)) {
       for (int q = lane; q < 16 * nb; q += 64) {
         const int rl = q / nb, b = q - rl * nb;
-        const int r = (rt << 4) + rl;
-        if (r >= L.MR) continue;
-        const double v = acc3[rl * MAXN + b];
+        const int rr = rb * BM + wave * 16 + rl;
+        if (rr >= L.MR) continue;
+        const double v = acc3[rl * ld3 + b];
         if (v != 0.0) {
-          const int i = row2i[r], f = r - L.f_row0[i];
+          const int i = row2i[rr], f = rr - L.f_row0[i];
           atomicAdd(P.Sbuf + L.f_dFBoff[i] + f * nb + b, v);
         }
       }
@@ -677,184 +716,183 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 //   P[(al,a)][(G,b)] = sum_{F,f} C_AF[al][a][f] w D_FB[f][b]   (term 2, kept units only)
 //   H1[a][b]  += sum_{al,G,g} P[(al,a)][(G,g)] Y_G[al][b][g]      -> Sigma(A,B)
 //   H2_G[a][g] = sum_{al,b}  P[(al,a)][(G,b)] Y_G[al][b][g]      -> Sigma(A,G)
-// A wave owns a 32-column strip.  The masked D panel of the strip (rows: the F's with a
-// kept unit in the strip) is staged once in the wave's scratch; the C operand is read
-// from the per-block transposed copy C^T[f][(al,a)] so a fragment is 16 consecutive
-// doubles; each wave computes 64x32 of P per pass (8 MFMAs per K step).  The Y
-// contractions of the epilogue are MFMA products over K = (al, column).
+// Per 64-column block: the masked D panel over the F's with a kept unit in the block is staged
+// once in the workgroup's scratch, P (all rows x 64) is formed by 128 x 64 block products with
+// C read from the per-block transposed copy, then contracted with Y on the matrix cores.
 __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
-                             const short *col2jj, double *wreg, int rows_cap) {
-  const int tid = threadIdx.x, lane = tid & 63;
+                             const short *col2jj, double *As, double *Bs, double *wg, int rows_cap,
+                             long long *kaddr /* LDS [rows_cap] */) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int M = L.PA * L.na, na = L.na, nb = L.nb, nF = L.nF, PA = L.PA;
-  const int ns = (L.NR + 31) >> 5;
-  double *Bp = wreg;                                                    // [rows_cap][32]
-  long long *kaddr = reinterpret_cast<long long *>(Bp + (long long)rows_cap * 32);  // [rows_cap]
-  double *Pb = reinterpret_cast<double *>(kaddr + rows_cap);            // [M][32]
+  const int ncb = (L.NR + BN - 1) / BN, nrb = (M + BM - 1) / BM;
+  double *panel = wg;                                   // [rows_cap][64]
+  double *Pb = panel + (long long)rows_cap * BN;        // [M][64]
   const double *CT = P.CTbuf;
   unsigned long long nmfma = 0;
-  const int kk = lane >> 4, l16 = lane & 15;
-  for (int cs = tid >> 6; cs < ns; cs += NW) {
-    const int c0 = cs << 5, c1 = min(c0 + 32, L.NR);
+  for (int cb = 0; cb < ncb; ++cb) {
+    const int c0 = cb * BN, c1 = min(c0 + BN, L.NR);
     const int jj0 = col2jj[c0], jj1 = col2jj[c1 - 1];
-    unsigned long long fset[4] = {0, 0, 0, 0};
-    bool t1any = false;
-    unsigned t2any = 0;
-    for (int base = 0; base < nF; base += 64) {
-      const int i = base + lane;
-      bool hit = false, h1 = false;
-      unsigned h2 = 0;
-      if (i < nF) {
-        for (int jj = jj0; jj <= jj1; ++jj) {
-          const int j = L.a_j[jj];
-          const int g0 = L.a_col0[jj], gb = g0 + L.g_n[j], g1 = L.a_col0[jj + 1];
-          const bool hasg = max(c0, g0) < min(c1, gb);
-          const bool hasb = max(c0, gb) < min(c1, g1);
+    // F set of the block, targets with work, active column tiles
+    if (tid == 0) {
+      L.blk_act = 0;
+      L.t1any = 0;
+      L.t2any = 0ull;
+    }
+    __syncthreads();
+    if (tid < nF) {
+      const int i = tid;
+      bool hit = false;
+      unsigned long long t2 = 0;
+      bool t1 = false;
+      for (int jj = jj0; jj <= jj1; ++jj) {
+        const int j = L.a_j[jj];
+        const int g0 = L.a_col0[jj], gb = g0 + L.g_n[j], g1 = L.a_col0[jj + 1];
+        const uint8_t bits = mask[i * L.nG + j];
+        if ((bits & kT1) && max(c0, g0) < min(c1, gb)) t1 = true;
+        if ((bits & kT2) && max(c0, gb) < min(c1, g1)) t2 |= 1ull << (jj - jj0);
+      }
+      hit = t1 || t2;
+      L.fpos[i] = hit ? 1 : 0;
+      if (t1) L.t1any = 1;
+      if (t2) atomicOr(&L.t2any, t2);
+      if (hit)
+        for (int ct = 0; ct < 4; ++ct) {
+          const int cl = c0 + ct * 16;
+          if (tile_has(L, mask, col2jj, i, cl, min(cl + 16, c1), kT1, kT2)) atomicOr(&L.blk_act, 1u << ct);
+        }
+    }
+    __syncthreads();
+    if (!L.blk_act) continue;
+    if (tid == 0) {
+      int kc = 0, m = 0;
+      for (int i = 0; i < nF; ++i)
+        if (L.fpos[i]) {
+          L.fsel[m] = (short)i;
+          L.fsrow[m] = kc;
+          ++m;
+          kc += L.f_n[i];
+        }
+      L.fsrow[m] = kc;
+      L.nsel = m;
+      L.kc = kc;
+    }
+    __syncthreads();
+    const int kc = L.kc, Kc = (kc + BK - 1) / BK * BK;
+    // stage the masked D panel and the C^T row addresses
+    for (int e = tid; e < Kc * BN; e += NT) {
+      const int k = e >> 6, cl = e & (BN - 1), c = c0 + cl;
+      double val = 0.0;
+      long long ka = 0;
+      if (k < kc) {
+        int lo = 0, hi = L.nsel - 1;  // last member whose first panel row is <= k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (L.fsrow[mid] <= k)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int i = L.fsel[lo], f = k - L.fsrow[lo];
+        ka = L.f_coff[i] + (long long)f * M;
+        if (c < c1) {
+          const int jj = col2jj[c], j = L.a_j[jj];
+          const int cc = c - L.a_col0[jj], ng = L.g_n[j];
           const uint8_t bits = mask[i * L.nG + j];
-          if (hasg && (bits & kT1)) h1 = true;
-          if (hasb && (bits & kT2)) h2 |= 1u << (jj - jj0);
-        }
-        hit = h1 || h2;
-      }
-      fset[base >> 6] = __ballot(hit);
-      t1any |= __any(h1);
-      for (int q = 0; q <= jj1 - jj0; ++q)
-        if (__any((h2 >> q) & 1u)) t2any |= 1u << q;
-    }
-    if (!(fset[0] | fset[1] | fset[2] | fset[3])) continue;
-    // stage the masked D panel and the C^T row addresses of the strip's F set
-    int kc = 0;
-    long long first = -1;
-    for (int w64 = 0; w64 < 4; ++w64) {
-      unsigned long long mm = fset[w64];
-      while (mm) {
-        const int i = (w64 << 6) + __builtin_ctzll(mm);
-        mm &= mm - 1;
-        const int nf = L.f_n[i];
-        if (first < 0) first = L.f_coff[i];
-        for (int e = lane; e < nf * 32; e += 64) {
-          const int f = e >> 5, cl = e & 31, c = c0 + cl;
-          double val = 0.0;
-          if (c < c1) {
-            const int jj = col2jj[c], j = L.a_j[jj];
-            const int cc = c - L.a_col0[jj], ng = L.g_n[j];
-            const uint8_t bits = mask[i * L.nG + j];
-            const double w = unit_weight(L, i, j);
-            if (cc < ng) {
-              if (bits & kT1) val = w * P.Dbuf[P.d_off[dfg[i * L.nG + j]] + f * ng + cc];
-            } else if (bits & kT2) {
-              val = w * P.Dbuf[L.f_dFBoff[i] + f * nb + (cc - ng)];
-            }
+          const double w = unit_weight(L, i, j);
+          if (cc < ng) {
+            if (bits & kT1) val = w * P.Dbuf[P.d_off[dfg[i * L.nG + j]] + f * ng + cc];
+          } else if (bits & kT2) {
+            val = w * P.Dbuf[L.f_dFBoff[i] + f * nb + (cc - ng)];
           }
-          Bp[(long long)(kc + f) * 32 + cl] = val;
         }
-        if (lane < nf) kaddr[kc + lane] = L.f_coff[i] + (long long)lane * M;
-        kc += nf;
+      } else {
+        ka = -1;
       }
+      panel[(long long)k * BN + cl] = val;
+      if (cl == 0) kaddr[k] = ka;
     }
-    const int Kc = (kc + 3) & ~3;
-    for (int e = lane; e < (Kc - kc) * 32; e += 64) Bp[(long long)kc * 32 + e] = 0.0;
-    if (lane < Kc - kc) kaddr[kc + lane] = first;
     __threadfence_block();
-    // P strip = C_A x panel, 64 rows per pass
-    for (int rg = 0; rg < M; rg += 64) {
-      d4 acc[4][2];
+    __syncthreads();
+    const unsigned colact = L.blk_act & 15u;
+    for (int rb = 0; rb < nrb; ++rb) {
+      const int r = rb * BM + (tid & (BM - 1));
+      const bool rok = r < M;
+      const int bcl = tid & (BN - 1);
+      d4 acc[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = d4{0, 0, 0, 0};
-      int rr[4];
-      bool rok[4];
+      for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
+      const unsigned act = (rb * BM + wave * 16 < M) ? colact : 0u;
+      wg_block_mm(
+          Kc,
+          [&](int k) {
+            const long long ka = kaddr[k];
+            return (rok && ka >= 0) ? CT[ka + r] : 0.0;
+          },
+          [&](int k) { return panel[(long long)k * BN + bcl]; }, act, As, Bs, acc);
+      nmfma += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        rr[u] = rg + 16 * u + l16;
-        rok[u] = rr[u] < M;
-      }
-      double a_c[4], b_c[2];
-      {
-        const long long bs = kaddr[kk];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a_c[u] = rok[u] ? CT[bs + rr[u]] : 0.0;
-        b_c[0] = Bp[kk * 32 + l16];
-        b_c[1] = Bp[kk * 32 + 16 + l16];
-      }
-      for (int k0 = 0; k0 < Kc; k0 += 4) {
-        const int k = k0 + 4 + kk;
-        double a_n[4] = {0.0, 0.0, 0.0, 0.0}, b_n[2] = {0.0, 0.0};
-        if (k0 + 4 < Kc) {
-          const long long bs = kaddr[k];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (rok[u]) a_n[u] = CT[bs + rr[u]];
-          b_n[0] = Bp[(long long)k * 32 + l16];
-          b_n[1] = Bp[(long long)k * 32 + 16 + l16];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          acc[u][0] = mfma64(a_c[u], b_c[0], acc[u][0]);
-          acc[u][1] = mfma64(a_c[u], b_c[1], acc[u][1]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a_c[u] = a_n[u];
-        b_c[0] = b_n[0];
-        b_c[1] = b_n[1];
-      }
-      nmfma += 8ull * (Kc >> 2);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = rg + 16 * u + kk + 4 * e;
-          if (row < M) {
-            Pb[(long long)row * 32 + l16] = acc[u][0][e];
-            Pb[(long long)row * 32 + 16 + l16] = acc[u][1][e];
-          }
+          const int row = rb * BM + wave * 16 + kk + 4 * e;
+          if (row < M) Pb[(long long)row * BN + v * 16 + l16] = (act & (1u << v)) ? acc[v][e] : 0.0;
         }
     }
     __threadfence_block();
-    // term 1: H1[a][b] += sum_{al, c in g-halves} P[(al,a)][c] Y_G(c)[al][b][g(c)]
-    if (t1any) {
+    __syncthreads();
+    // contractions with Y: work items (target, alpha part); target 0 = term 1, 1+q = term 2 of jj0+q
+    const unsigned long long t2m = L.t2any;
+    const int nt2 = jj1 - jj0 + 1;
+    const int parts = NW;
+    const int nwork = (L.t1any ? parts : 0) + nt2;
+    for (int wi = wave; wi < nwork; wi += NW) {
+      const bool is1 = L.t1any && wi < parts;
       d4 h = {0, 0, 0, 0};
-      for (int al = 0; al < PA; ++al)
-        for (int cg = 0; cg < 32; cg += 4) {
-          const int cl = cg + kk, c = c0 + cl;
-          double av = 0.0, bv = 0.0;
-          if (c < c1) {
-            const int jj = col2jj[c], j = L.a_j[jj];
-            const int cc = c - L.a_col0[jj], ng = L.g_n[j];
-            if (cc < ng) {
-              if (l16 < na) av = Pb[(long long)(al * na + l16) * 32 + cl];
-              if (l16 < nb) bv = slot[L.a_y[jj] + ((long long)al * nb + l16) * ng + cc];
+      if (is1) {
+        const int al0 = wi * PA / parts, al1 = (wi + 1) * PA / parts;
+        for (int al = al0; al < al1; ++al)
+          for (int cg = 0; cg < c1 - c0; cg += 4) {
+            const int cl = cg + kk, c = c0 + cl;
+            double av = 0.0, bv = 0.0;
+            if (c < c1) {
+              const int jj = col2jj[c], j = L.a_j[jj];
+              const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+              if (cc < ng) {
+                if (l16 < na) av = Pb[(long long)(al * na + l16) * BN + cl];
+                if (l16 < nb) bv = slot[L.a_y[jj] + ((long long)al * nb + l16) * ng + cc];
+              }
             }
+            h = mfma64(av, bv, h);
           }
-          h = mfma64(av, bv, h);
+        nmfma += (unsigned long long)(al1 - al0) * ((c1 - c0 + 3) >> 2);
+        for (int e = 0; e < 4; ++e) {
+          const int a = kk + 4 * e;
+          if (a < na && l16 < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + l16], h[e]);
         }
-      nmfma += (unsigned long long)PA * 8;
-      for (int e = 0; e < 4; ++e) {
-        const int a = kk + 4 * e;
-        if (a < na && l16 < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + l16], h[e]);
+      } else {
+        const int q = wi - (L.t1any ? parts : 0);
+        if (!((t2m >> q) & 1ull)) continue;
+        const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
+        const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
+        const int bc0 = max(c0, gb), bc1 = min(c1, g1);
+        for (int al = 0; al < PA; ++al)
+          for (int cbb = bc0; cbb < bc1; cbb += 4) {
+            const int c = cbb + kk;
+            double av = 0.0, bv = 0.0;
+            if (c < bc1) {
+              if (l16 < na) av = Pb[(long long)(al * na + l16) * BN + (c - c0)];
+              if (l16 < ng) bv = slot[L.a_y[jj] + ((long long)al * nb + (c - gb)) * ng + l16];
+            }
+            h = mfma64(av, bv, h);
+          }
+        nmfma += (unsigned long long)PA * ((bc1 - bc0 + 3) >> 2);
+        for (int e = 0; e < 4; ++e) {
+          const int a = kk + 4 * e;
+          if (a < na && l16 < ng && h[e] != 0.0) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * ng + l16, -h[e]);
+        }
       }
     }
-    // term 2: H2_G[a][g] = sum_{al, b in G's b-half} P[(al,a)][(G,b)] Y_G[al][b][g]
-    for (int q = 0; q <= jj1 - jj0; ++q) {
-      if (!((t2any >> q) & 1u)) continue;
-      const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
-      const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
-      const int bc0 = max(c0, gb), bc1 = min(c1, g1);
-      d4 h = {0, 0, 0, 0};
-      for (int al = 0; al < PA; ++al)
-        for (int cb = bc0; cb < bc1; cb += 4) {
-          const int c = cb + kk;
-          double av = 0.0, bv = 0.0;
-          if (c < bc1) {
-            if (l16 < na) av = Pb[(long long)(al * na + l16) * 32 + (c - c0)];
-            if (l16 < ng) bv = slot[L.a_y[jj] + ((long long)al * nb + (c - gb)) * ng + l16];
-          }
-          h = mfma64(av, bv, h);
-        }
-      nmfma += (unsigned long long)PA * ((bc1 - bc0 + 3) >> 2);
-      for (int e = 0; e < 4; ++e) {
-        const int a = kk + 4 * e;
-        if (a < na && l16 < ng && h[e] != 0.0) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * ng + l16, -h[e]);
-      }
-    }
+    __syncthreads();
   }
   if (lane == 0 && nmfma) atomicAdd(&L.cnt[kCntMfmaL], nmfma);
 }
@@ -865,7 +903,11 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
   extern __shared__ double dyn[];
   uint8_t *row2i = reinterpret_cast<uint8_t *>(dyn);
   short *col2jj = reinterpret_cast<short *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap);
-  double *accw = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap + 2 * kp.cols_cap);
+  double *As = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap + 2 * kp.cols_cap);
+  double *Bs = As + 2 * BK * BM;
+  double *acc3 = Bs + 2 * BK * BN;  // [NW][16][ld3]
+  long long *kaddr = reinterpret_cast<long long *>(acc3 + NW * 16 * kp.ld3);  // [rows_cap]
+  const int dyn_doubles = 2 * BK * BM + 2 * BK * BN + NW * 16 * kp.ld3;
   __shared__ int s_item;
   const int tid = threadIdx.x;
   double *slot = P.scratch + (long long)blockIdx.x * P.slot_doubles;
@@ -1006,10 +1048,10 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     __syncthreads();
     {
       // V_AB in LDS when it fits in the accumulator region (not in use in this phase)
-      const bool vlds = L.PA * L.PB <= NW * kp.acc_doubles;
-      const double *Vsrc = vlds ? accw : P.Vbuf + L.voff;
+      const bool vlds = L.PA * L.PB <= dyn_doubles;
+      const double *Vsrc = vlds ? As : P.Vbuf + L.voff;
       if (vlds)
-        for (int q = tid; q < L.PA * L.PB; q += NT) accw[q] = P.Vbuf[L.voff + q];
+        for (int q = tid; q < L.PA * L.PB; q += NT) As[q] = P.Vbuf[L.voff + q];
       __syncthreads();
       for (int jj = tid >> 6; jj < L.nGa; jj += NW) gside_wave(P, L, slot, jj, Vsrc);
       __syncthreads();
@@ -1069,11 +1111,10 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     __syncthreads();
     tick(2);
     if (L.nGa > 0) {
-      phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, accw, kp.acc_doubles);
+      phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3);
       __syncthreads();
       tick(3);
-      phase_gemm_l(P, L, slot, dfg, mask, col2jj, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles,
-                   kp.rows_cap);
+      phase_gemm_l(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr);
     }
     __syncthreads();
     tick(4);
@@ -1361,10 +1402,15 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ D, co
 
 // ---------------------------------------------------------------------------------------------
 // launch wrappers (host side)
-hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles, long long wave_off,
-                       long long wave_doubles, hipStream_t s) {
-  KParams kp{rows_cap, cols_cap, acc_doubles, wave_off, wave_doubles};
-  const size_t dyn = (size_t)rows_cap + 2 * (size_t)cols_cap + (size_t)NW * acc_doubles * sizeof(double);
+size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3) {
+  return (size_t)rows_cap + 2 * (size_t)cols_cap + (size_t)(2 * BK * BM + 2 * BK * BN + NW * 16 * ld3) * sizeof(double) +
+         (size_t)rows_cap * sizeof(long long);
+}
+
+hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
+                       long long wave_doubles, long long wg_off, hipStream_t s) {
+  KParams kp{rows_cap, cols_cap, ld3, wave_off, wave_doubles, wg_off};
+  const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
   hipError_t e = hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_main, dim3(n_slots), dim3(NT), dyn, s, P, kp);

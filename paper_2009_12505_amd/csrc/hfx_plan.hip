@@ -20,8 +20,9 @@
 #include "hfx_internal.h"
 
 namespace hfx {
-hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int acc_doubles, long long wave_off,
-                       long long wave_doubles, hipStream_t s);
+hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
+                       long long wave_doubles, long long wg_off, hipStream_t s);
+size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3);
 hipError_t launch_ctrans(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
                          const int *nao, const int *nabf, int nC, double *CT, hipStream_t s);
 size_t main_static_lds();
@@ -119,8 +120,8 @@ struct hfx_plan {
   int64_t n_items = 0;
 
   DevPlan dp{};
-  int n_slots = 0, rows_cap = 0, cols_cap = 0, acc_doubles = 0;
-  long long wave_off = 0, wave_doubles = 0;
+  int n_slots = 0, rows_cap = 0, cols_cap = 0, ld3 = 0;
+  long long wave_off = 0, wave_doubles = 0, wg_off = 0;
   double *part = nullptr;  // energy partial sums
   int part_blocks = 1024;
   double *staging = nullptr;  // pinned host staging for D
@@ -568,14 +569,13 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     return fail(HFX_ERR_UNSUPPORTED, "neighbour lists too long for the decode tables");
   const int64_t nfg = (int64_t)max_nbr * max_nbr;
   p->wave_off = (nfg + 1) / 2 + (nfg + 7) / 8 + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
-  p->wave_doubles = (std::max<int64_t>((int64_t)p->rows_cap * 33 + (int64_t)max_p * max_n * 32,
-                                       16 * (int64_t)main_maxn() * main_maxn()) +
-                     64 + 31) / 32 * 32;
-  const int64_t slot = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
+  p->wave_doubles = (16 * (int64_t)main_maxn() * main_maxn() + 64 + 31) / 32 * 32;
+  p->wg_off = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
+  const int64_t wg_doubles = (int64_t)p->rows_cap * 64 + (int64_t)max_p * max_n * 64 + 64;
+  const int64_t slot = p->wg_off + wg_doubles;
   (void)min_n;
-  p->acc_doubles = 16 * main_maxn();
-  const size_t lds = main_static_lds() + (size_t)p->rows_cap + 2 * (size_t)p->cols_cap +
-                     (size_t)main_nwaves() * p->acc_doubles * sizeof(double);
+  p->ld3 = max_n;
+  const size_t lds = main_static_lds() + main_dyn_lds(p->rows_cap, p->cols_cap, p->ld3);
   if (lds > 160 * 1024)
     return fail(HFX_ERR_UNSUPPORTED, "workgroup would need %zu bytes of LDS (limit 163840)", lds);
 
@@ -781,8 +781,8 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
   HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
   HIPCHK(p, launch_reset(P.ticket, P.counters, P.flops, p->stream));
   HIPCHK(p, hipEventRecord(p->ev1, p->stream));
-  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->acc_doubles, p->wave_off, p->wave_doubles,
-                                          p->stream));
+  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles,
+                                          p->wg_off, p->stream));
   HIPCHK(p, hipEventRecord(p->ev2, p->stream));
   for (int c = 0; c < p->n_cells; ++c) {
     const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
