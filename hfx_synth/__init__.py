@@ -293,57 +293,97 @@ def _unique_keys(sr, sc, q):
     return uniq, inv.reshape(-1)
 
 
-def _build(kind, cell, row, col, R, d, seed, p, spd):
-    sr = cell.species[row]
-    sc = cell.species[col]
+def _draw(kind, tab, sr, sc, d, seed, p, spd):
+    """Block data for pairs with row/column species sr, sc and displacement d: one draw per
+    distinct (species pair, quantised displacement), vectorised over the draws of a species
+    pair.  Returns (data, offset of each pair's block)."""
     q = _quant(d)
     uniq, inv = _unique_keys(sr, sc, q)
-    sizes = []
-    datas = []
-    for u in uniq:
-        a, b = int(u[0]), int(u[1])
-        qd = u[2:5]
-        flip = False
-        if kind in ("V", "D") and (b, *(-qd).tolist()) < (a, *qd.tolist()):
-            # V(R) = V(-R)^T and D(R) = D(-R)^T exactly: draw the canonical orientation, transpose
-            a, b, qd, flip = b, a, -qd, True
-        dv = qd.astype(np.float64) * _QUANT
-        A, B = spd[a], spd[b]
-        if kind == "C":
-            dist = float(np.linalg.norm(dv))
-            z = keyed_normal(key(seed, TAG_C, a, b, qd[0], qd[1], qd[2]), A.n_abf * A.n_ao * B.n_ao)[0]
-            z = z.reshape(A.n_abf, A.n_ao, B.n_ao)
-            if np.all(qd == 0):
-                z = (z + z.transpose(0, 2, 1)) / math.sqrt(2.0)
-            blk = z * math.exp(-dist / p.c_decay)
-        elif kind == "V":
-            rv = np.linalg.norm(dv[None, None, :] + B.s[None, :, :] - A.s[:, None, :], axis=2)
-            blk = (1.0 - p.lam) * kernel_v(rv, p) * (A.w @ B.w.T)
-            if np.all(qd == 0) and a == b:
-                blk = blk + p.lam * np.eye(A.n_abf)
-        else:
-            rd = np.linalg.norm(dv[None, None, :] + B.t[None, :, :] - A.t[:, None, :], axis=2)
-            blk = kernel_d(rd, p) * (A.u @ B.u.T)
-        if flip:
-            blk = blk.T
-        datas.append(np.ascontiguousarray(blk, np.float64).reshape(-1))
-        sizes.append(blk.size)
-    sizes = np.asarray(sizes, np.int64)
-    uoff = np.zeros(len(sizes), np.int64)
-    if len(sizes):
+    nu = uniq.shape[0]
+    a_all, b_all, q_all = uniq[:, 0].copy(), uniq[:, 1].copy(), uniq[:, 2:5].copy()
+    flip = np.zeros(nu, bool)
+    if kind in ("V", "D"):
+        # V(R) = V(-R)^T and D(R) = D(-R)^T exactly: draw the canonical orientation, transpose
+        # (canonical: (species of col, -q) does not precede (species of row, q) lexicographically)
+        nq = -q_all
+        lt = (nq[:, 0] < q_all[:, 0]) | ((nq[:, 0] == q_all[:, 0]) & (
+            (nq[:, 1] < q_all[:, 1]) | ((nq[:, 1] == q_all[:, 1]) & (nq[:, 2] < q_all[:, 2]))))
+        flip = (b_all < a_all) | ((b_all == a_all) & lt)
+        a_all[flip], b_all[flip] = uniq[flip, 1], uniq[flip, 0]
+        q_all[flip] = nq[flip]
+    if kind == "C":
+        sizes = np.array([tab[int(x)][1] * tab[int(x)][0] * tab[int(y)][0] for x, y in zip(uniq[:, 0], uniq[:, 1])],
+                         np.int64)
+    elif kind == "V":
+        sizes = np.array([tab[int(x)][1] * tab[int(y)][1] for x, y in zip(uniq[:, 0], uniq[:, 1])], np.int64)
+    else:
+        sizes = np.array([tab[int(x)][0] * tab[int(y)][0] for x, y in zip(uniq[:, 0], uniq[:, 1])], np.int64)
+    uoff = np.zeros(nu, np.int64)
+    if nu:
         uoff[1:] = np.cumsum(sizes)[:-1]
-    data = np.concatenate(datas) if datas else np.zeros(0)
-    return Blocks(row.astype(np.int32), col.astype(np.int32), R.astype(np.int32), uoff[inv], data, kind)
+    data = np.empty(int(sizes.sum()), np.float64)
+    for a in np.unique(a_all):
+        for b in np.unique(b_all):
+            sel = np.nonzero((a_all == a) & (b_all == b))[0]
+            if sel.size == 0:
+                continue
+            A, B = spd[int(a)], spd[int(b)]
+            qd = q_all[sel]
+            dv = qd.astype(np.float64) * _QUANT                      # (n,3)
+            if kind == "C":
+                z = keyed_normal(key(seed, TAG_C, a, b, qd[:, 0], qd[:, 1], qd[:, 2]), A.n_abf * A.n_ao * B.n_ao)
+                z = z.reshape(-1, A.n_abf, A.n_ao, B.n_ao)
+                onsite = np.all(qd == 0, axis=1)
+                if np.any(onsite):
+                    z[onsite] = (z[onsite] + z[onsite].transpose(0, 1, 3, 2)) / math.sqrt(2.0)
+                blk = z * np.exp(-np.linalg.norm(dv, axis=1) / p.c_decay)[:, None, None, None]
+            elif kind == "V":
+                rv = np.linalg.norm(dv[:, None, None, :] + B.s[None, None, :, :] - A.s[None, :, None, :], axis=3)
+                blk = (1.0 - p.lam) * kernel_v(rv, p) * (A.w @ B.w.T)[None]
+                onsite = np.all(qd == 0, axis=1) & (a == b)
+                if np.any(onsite):
+                    blk[onsite] += p.lam * np.eye(A.n_abf)
+            else:
+                rd = np.linalg.norm(dv[:, None, None, :] + B.t[None, None, :, :] - A.t[None, :, None, :], axis=3)
+                blk = kernel_d(rd, p) * (A.u @ B.u.T)[None]
+            n = sel.size
+            size = int(blk[0].size)
+            out = np.empty((n, size), np.float64)
+            fl = flip[sel]
+            out[~fl] = blk[~fl].reshape(-1, size)
+            if np.any(fl):
+                out[fl] = blk[fl].transpose(0, 2, 1).reshape(-1, size)
+            pos = uoff[sel][:, None] + np.arange(size)[None, :]
+            data[pos] = out
+    return data, uoff[inv]
+
+
+def build_blocks_multi(cells, seed: int, p: Params):
+    """C, V and D blocks for cells that share one species table and one keyed draw:
+    identical blocks (same species pair and displacement) share storage within and
+    across cells."""
+    tab = cells[0].species_table
+    spd = [_SpeciesData(seed, s, na, nb, p) for s, (na, nb) in enumerate(tab)]
+    out = {"C": [], "V": [], "D": []}
+    for kind, rc in (("C", p.r_c), ("V", p.r_v), ("D", p.r_d)):
+        pairs = [enumerate_pairs(c.lattice, c.pos, rc - 1e-9 if kind != "C" else rc) for c in cells]
+        sr = np.concatenate([c.species[pr[0]] for c, pr in zip(cells, pairs)])
+        sc = np.concatenate([c.species[pr[1]] for c, pr in zip(cells, pairs)])
+        d = np.concatenate([pr[3] for pr in pairs])
+        data, off = _draw(kind, tab, sr, sc, d, seed, p, spd)
+        k0 = 0
+        for (row, col, R, _), c in zip(pairs, cells):
+            n = row.shape[0]
+            out[kind].append(Blocks(row.astype(np.int32), col.astype(np.int32), R.astype(np.int32), off[k0:k0 + n],
+                                    data, kind))
+            k0 += n
+    return out["C"], out["V"], out["D"]
 
 
 def build_blocks(cell: Cell, seed: int, p: Params):
     """C, V and D blocks for one cell (aliased storage for identical blocks)."""
-    spd = [_SpeciesData(seed, s, na, nb, p) for s, (na, nb) in enumerate(cell.species_table)]
-    out = {}
-    for kind, rc in (("C", p.r_c), ("V", p.r_v), ("D", p.r_d)):
-        row, col, R, d = enumerate_pairs(cell.lattice, cell.pos, rc - 1e-9 if kind != "C" else rc)
-        out[kind] = _build(kind, cell, row, col, R, d, seed, p, spd)
-    return out["C"], out["V"], out["D"]
+    C, V, D = build_blocks_multi([cell], seed, p)
+    return C[0], V[0], D[0]
 
 
 # ----------------------------------------------------------------------------- configs
@@ -370,7 +410,7 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
     cfg3      512 atoms (4^3 conventional cells), 13/60, C within 16 bohr, eps 1e-6 (or 1e-4)
     cfg3prim  the 2-atom primitive cell of cfg3 with identical keyed blocks
     cfg4      48 cells of 1..3 x 1..3 x 1..3 conventional cells, species 13/60 and 27/100
-              drawn per site with p = 1/2, C within 12 bohr, eps 1e-4
+              drawn per site with p = 1/2, C within 12 bohr, V within 24, D within 30, eps 1e-4
     cfg5      4096 atoms (8^3 conventional cells), 13/60, eps 1e-6
     tiny      user-sized cells for tests (keywords: kind, n, species_table, r_c, r_v, r_d, eps)
     """
@@ -390,7 +430,8 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
             cells = [make_cell("conventional", (n, n, n), species_table=((13, nabf),))]
         th = 1e-6 if eps is None else eps
     elif name == "cfg4":
-        p = Params(r_c=12.0, r_v=36.0, r_d=45.0)
+        # eps 1e-4: V beyond ~20 bohr and D beyond ~28 bohr are below it before tapering
+        p = Params(r_c=12.0, r_v=24.0, r_d=30.0)
         ncell = kw.pop("n_cells", 48)
         cells = []
         for c in range(ncell):
@@ -410,12 +451,7 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
         th = 0.0 if eps is None else eps
     if kw:
         raise TypeError(f"unknown keywords {sorted(kw)}")
-    C, V, D = [], [], []
-    for ci, cell in enumerate(cells):
-        # cells of one batched workload get their own key stream
-        cs = seed if len(cells) == 1 else int(key(seed, ci)[0] & np.uint64(0x7FFFFFFFFFFF))
-        c, v, d = build_blocks(cell, cs, p)
-        C.append(c), V.append(v), D.append(d)
+    C, V, D = build_blocks_multi(cells, seed, p)
     thr = dict(eps_C=th, eps_V=th, eps_D=th, eps_cs_eri=th, eps_cs_mat=th)
     return Workload(name, seed, cells, C, V, D, thr, p)
 

@@ -210,7 +210,25 @@ static void c_norms(const double *c, int P, int na, int nf, double *nA, double *
 static const double *blk(const ref_blocks *b, int64_t k) { return b->data + b->off[k]; }
 
 /* Q_AF = sqrt(max_{a,f} (Aa Ff | Aa Ff)) with the full ERI of the pair
- * expansion (eq. LRI) under set semantics (Sec. III C 2, eq. CS-ERI). */
+ * expansion (eq. LRI) under set semantics (Sec. III C 2, eq. CS-ERI):
+ *   (Aa Ff|Aa Ff) = sum_{X,Y in {A,F}} sum_{alpha,beta} u_X[alpha] V_XY[alpha][beta] u_Y[beta],
+ *   u_A[alpha] = C_AF[alpha][a][f],  u_F[beta] = C_FA[beta][f][a]  (F's part absent when F is A).
+ * Evaluated for all (a,f) at once: W = V_XY U_Y, then the column dots with U_X. */
+static void acc_quad(const double *Ux, int Px, const double *V, const double *Uy, int Py, int n, double *val,
+                     double *W) {
+  for (int al = 0; al < Px; ++al) {
+    double *w = W + (int64_t)al * n;
+    for (int q = 0; q < n; ++q) w[q] = 0.0;
+    for (int be = 0; be < Py; ++be) {
+      const double v = V[al * Py + be];
+      const double *u = Uy + (int64_t)be * n;
+      for (int q = 0; q < n; ++q) w[q] += v * u[q];
+    }
+    const double *ux = Ux + (int64_t)al * n;
+    for (int q = 0; q < n; ++q) val[q] += ux[q] * w[q];
+  }
+}
+
 static double q_value(const ref_ctx *x, int64_t kc) {
   const int32_t A = x->C.row[kc], F = x->C.col[kc];
   const int32_t *R = &x->C.R[3 * kc];
@@ -231,35 +249,35 @@ static double q_value(const ref_ctx *x, int64_t kc) {
     k = index_find(&x->iV, F, F, 0, 0, 0);
     if (k >= 0 && x->keepV[k]) vFF = blk(&x->V, k);
   }
+  const int n = na * nf;
+  const int Pm = PA > PF ? PA : PF;
+  double *val = (double *)calloc((size_t)n, sizeof(double));
+  double *W = (double *)malloc(sizeof(double) * (size_t)Pm * n);
+  double *U2 = NULL;
+  /* U_A = C_AF viewed as [alpha][(a,f)] */
+  if (vAA) acc_quad(cAF, PA, vAA, cAF, PA, n, val, W);
+  if (!onsite && cFA) {
+    /* U_F[beta][(a,f)] = C_FA[beta][f][a] */
+    U2 = (double *)malloc(sizeof(double) * (size_t)PF * n);
+    for (int be = 0; be < PF; ++be)
+      for (int a = 0; a < na; ++a)
+        for (int f = 0; f < nf; ++f) U2[((int64_t)be * na + a) * nf + f] = cFA[((int64_t)be * nf + f) * na + a];
+    if (vAF) acc_quad(cAF, PA, vAF, U2, PF, n, val, W);
+    if (vFA) acc_quad(U2, PF, vFA, cAF, PA, n, val, W);
+    if (vFF) acc_quad(U2, PF, vFF, U2, PF, n, val, W);
+  }
   double best = 0.0;
-  double *u = (double *)malloc(sizeof(double) * (size_t)(PA + PF));
-  for (int a = 0; a < na; ++a)
-    for (int f = 0; f < nf; ++f) {
-      /* u = [C^{A}_{Aa,Ff} ; C^{F}_{Ff,Aa}] */
-      for (int al = 0; al < PA; ++al) u[al] = cAF[((int64_t)al * na + a) * nf + f];
-      for (int be = 0; be < PF; ++be) u[PA + be] = cFA ? cFA[((int64_t)be * nf + f) * na + a] : 0.0;
-      double val = 0.0;
-      if (vAA)
-        for (int al = 0; al < PA; ++al)
-          for (int be = 0; be < PA; ++be) val += u[al] * vAA[al * PA + be] * u[be];
-      if (!onsite) {
-        if (vAF)
-          for (int al = 0; al < PA; ++al)
-            for (int be = 0; be < PF; ++be) val += u[al] * vAF[al * PF + be] * u[PA + be];
-        if (vFA)
-          for (int al = 0; al < PF; ++al)
-            for (int be = 0; be < PA; ++be) val += u[PA + al] * vFA[al * PA + be] * u[be];
-        if (vFF)
-          for (int al = 0; al < PF; ++al)
-            for (int be = 0; be < PF; ++be) val += u[PA + al] * vFF[al * PF + be] * u[PA + be];
-      }
-      if (val > best) best = val;
-    }
-  free(u);
+  for (int q = 0; q < n; ++q)
+    if (val[q] > best) best = val[q];
+  free(val);
+  free(W);
+  free(U2);
   return sqrt(best);
 }
 
-static int ctx_setup(ref_ctx *x) {
+/* need_q[atom]: rows whose C blocks can enter a quartet of the build (home atoms A and the
+ * partners B of their kept V blocks); need_v[atom]: rows of the work items (home atoms). */
+static int ctx_setup(ref_ctx *x, const unsigned char *need_q, const unsigned char *need_v) {
   if (index_build(&x->iC, &x->C, x->n_atoms) || index_build(&x->iV, &x->V, x->n_atoms) ||
       index_build(&x->iD, &x->D, x->n_atoms))
     return -1;
@@ -285,17 +303,17 @@ static int ctx_setup(ref_ctx *x) {
     const int P = x->nabf[A], na = x->nao[A], nf = x->nao[F];
     const double *c = blk(&x->C, k);
     x->keepC[k] = pre ? (max_abs(c, (int64_t)P * na * nf) > x->eps_C) : 1;
-    c_norms(c, P, na, nf, &x->nA[k], &x->gA[k], &x->nF[k], &x->gF[k]);
+    if (need_q[A]) c_norms(c, P, na, nf, &x->nA[k], &x->gA[k], &x->nF[k], &x->gF[k]);
   }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < nV; ++k) {
     const int A = x->V.row[k], B = x->V.col[k];
     const double *v = blk(&x->V, k);
     x->keepV[k] = pre ? (max_abs(v, (int64_t)x->nabf[A] * x->nabf[B]) > x->eps_V) : 1;
-    x->gV[k] = sqrt_gram_norm(v, x->nabf[A], x->nabf[B], x->nabf[B]);
+    x->gV[k] = need_v[A] ? sqrt_gram_norm(v, x->nabf[A], x->nabf[B], x->nabf[B]) : 0.0;
   }
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t k = 0; k < nC; ++k) x->Q[k] = q_value(x, k);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t k = 0; k < nC; ++k) x->Q[k] = need_q[x->C.row[k]] ? q_value(x, k) : 0.0;
   int64_t o = 0;
   for (int64_t k = 0; k < nD; ++k) {
     x->sig_off[k] = o;
@@ -728,7 +746,21 @@ int hfxref_build(int32_t n_atoms, const int32_t *nao, const int32_t *nabf, int64
 #else
   (void)n_threads;
 #endif
-  int rc = ctx_setup(&x);
+  unsigned char *need_v = (unsigned char *)calloc((size_t)n_atoms + 1, 1);
+  unsigned char *need_q = (unsigned char *)calloc((size_t)n_atoms + 1, 1);
+  if (!need_v || !need_q) return -1;
+  if (home) {
+    for (int32_t i = 0; i < n_home; ++i)
+      if (home[i] >= 0 && home[i] < n_atoms) need_v[home[i]] = need_q[home[i]] = 1;
+    for (int64_t k = 0; k < nV; ++k)
+      if (need_v[Vrow[k]]) need_q[Vcol[k]] = 1;
+  } else {
+    memset(need_v, 1, (size_t)n_atoms);
+    memset(need_q, 1, (size_t)n_atoms);
+  }
+  int rc = ctx_setup(&x, need_q, need_v);
+  free(need_v);
+  free(need_q);
   if (rc == 0) {
     ctx_set_d(&x);
     if (dropped_bound) memset(dropped_bound, 0, sizeof(double) * (size_t)nD);

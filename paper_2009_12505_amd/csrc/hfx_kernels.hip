@@ -248,9 +248,9 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
   double t4max = 0.0;
   if (L.okAB) {
     double *T4 = slot + L.a_t4[jj];
-    for (int a0 = 0; a0 < na; a0 += 16)
-      for (int g0 = 0; g0 < ng; g0 += 16) {
-        double sq = 0.0;
+    for (int g0 = 0; g0 < ng; g0 += 16) {
+      double sq = 0.0;  // sum over (al, a) of T4^2 for column g = g0 + l16 (this lane's rows)
+      for (int a0 = 0; a0 < na; a0 += 16) {
         for (int al = 0; al < PA; ++al) {
           const double *Ya = Y + (long long)al * N;
           const d4 h = tile_mm(
@@ -265,10 +265,11 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
           }
         }
         nm += (unsigned long long)PA * ((nb + 3) >> 2);
-        sq += __shfl_xor(sq, 16);
-        sq += __shfl_xor(sq, 32);
-        t4max = fmax(t4max, wave_max(sq));
       }
+      sq += __shfl_xor(sq, 16);
+      sq += __shfl_xor(sq, 32);
+      t4max = fmax(t4max, wave_max(sq));
+    }
   }
   // T3[(al,a)][b] = sum_g D_AG[a][g] Y[al][b][g]
   double t3max = 0.0;
@@ -276,9 +277,9 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
   if (dAG >= 0 && P.keepD[dAG]) {
     const double *DAG = P.Dbuf + L.g_dAGoff[j];
     double *T3 = slot + L.a_t3[jj];
-    for (int a0 = 0; a0 < na; a0 += 16)
-      for (int b0 = 0; b0 < nb; b0 += 16) {
-        double sq = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 16) {
+      double sq = 0.0;  // sum over (al, a) of T3^2 for column b = b0 + l16 (this lane's rows)
+      for (int a0 = 0; a0 < na; a0 += 16) {
         for (int al = 0; al < PA; ++al) {
           const double *Ya = Y + (long long)al * N;
           const d4 h = tile_mm(
@@ -293,10 +294,11 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
           }
         }
         nm += (unsigned long long)PA * ((ng + 3) >> 2);
-        sq += __shfl_xor(sq, 16);
-        sq += __shfl_xor(sq, 32);
-        t3max = fmax(t3max, wave_max(sq));
       }
+      sq += __shfl_xor(sq, 16);
+      sq += __shfl_xor(sq, 32);
+      t3max = fmax(t3max, wave_max(sq));
+    }
   }
   // N1[b][g][g'] = sum_al Y[al][b][g] Y[al][b][g'];  Yb^2 = max_b trace N1[b]
   double *N1 = slot + L.a_n1[jj];
@@ -847,49 +849,56 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
     const int nwork = (L.t1any ? parts : 0) + nt2;
     for (int wi = wave; wi < nwork; wi += NW) {
       const bool is1 = L.t1any && wi < parts;
-      d4 h = {0, 0, 0, 0};
       if (is1) {
         const int al0 = wi * PA / parts, al1 = (wi + 1) * PA / parts;
-        for (int al = al0; al < al1; ++al)
-          for (int cg = 0; cg < c1 - c0; cg += 4) {
-            const int cl = cg + kk, c = c0 + cl;
-            double av = 0.0, bv = 0.0;
-            if (c < c1) {
-              const int jj = col2jj[c], j = L.a_j[jj];
-              const int cc = c - L.a_col0[jj], ng = L.g_n[j];
-              if (cc < ng) {
-                if (l16 < na) av = Pb[(long long)(al * na + l16) * BN + cl];
-                if (l16 < nb) bv = slot[L.a_y[jj] + ((long long)al * nb + l16) * ng + cc];
+        for (int a0 = 0; a0 < na; a0 += 16)
+          for (int b0 = 0; b0 < nb; b0 += 16) {
+            d4 h = {0, 0, 0, 0};
+            for (int al = al0; al < al1; ++al)
+              for (int cg = 0; cg < c1 - c0; cg += 4) {
+                const int cl = cg + kk, c = c0 + cl;
+                double av = 0.0, bv = 0.0;
+                if (c < c1) {
+                  const int jj = col2jj[c], j = L.a_j[jj];
+                  const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+                  if (cc < ng) {
+                    if (a0 + l16 < na) av = Pb[(long long)(al * na + a0 + l16) * BN + cl];
+                    if (b0 + l16 < nb) bv = slot[L.a_y[jj] + ((long long)al * nb + b0 + l16) * ng + cc];
+                  }
+                }
+                h = mfma64(av, bv, h);
               }
+            nmfma += (unsigned long long)(al1 - al0) * ((c1 - c0 + 3) >> 2);
+            for (int e = 0; e < 4; ++e) {
+              const int a = a0 + kk + 4 * e, b = b0 + l16;
+              if (a < na && b < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + b], h[e]);
             }
-            h = mfma64(av, bv, h);
           }
-        nmfma += (unsigned long long)(al1 - al0) * ((c1 - c0 + 3) >> 2);
-        for (int e = 0; e < 4; ++e) {
-          const int a = kk + 4 * e;
-          if (a < na && l16 < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + l16], h[e]);
-        }
       } else {
         const int q = wi - (L.t1any ? parts : 0);
         if (!((t2m >> q) & 1ull)) continue;
         const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
         const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
         const int bc0 = max(c0, gb), bc1 = min(c1, g1);
-        for (int al = 0; al < PA; ++al)
-          for (int cbb = bc0; cbb < bc1; cbb += 4) {
-            const int c = cbb + kk;
-            double av = 0.0, bv = 0.0;
-            if (c < bc1) {
-              if (l16 < na) av = Pb[(long long)(al * na + l16) * BN + (c - c0)];
-              if (l16 < ng) bv = slot[L.a_y[jj] + ((long long)al * nb + (c - gb)) * ng + l16];
+        for (int a0 = 0; a0 < na; a0 += 16)
+          for (int g0 = 0; g0 < ng; g0 += 16) {
+            d4 h = {0, 0, 0, 0};
+            for (int al = 0; al < PA; ++al)
+              for (int cbb = bc0; cbb < bc1; cbb += 4) {
+                const int c = cbb + kk;
+                double av = 0.0, bv = 0.0;
+                if (c < bc1) {
+                  if (a0 + l16 < na) av = Pb[(long long)(al * na + a0 + l16) * BN + (c - c0)];
+                  if (g0 + l16 < ng) bv = slot[L.a_y[jj] + ((long long)al * nb + (c - gb)) * ng + g0 + l16];
+                }
+                h = mfma64(av, bv, h);
+              }
+            nmfma += (unsigned long long)PA * ((bc1 - bc0 + 3) >> 2);
+            for (int e = 0; e < 4; ++e) {
+              const int a = a0 + kk + 4 * e, g = g0 + l16;
+              if (a < na && g < ng && h[e] != 0.0) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * ng + g, -h[e]);
             }
-            h = mfma64(av, bv, h);
           }
-        nmfma += (unsigned long long)PA * ((bc1 - bc0 + 3) >> 2);
-        for (int e = 0; e < 4; ++e) {
-          const int a = kk + 4 * e;
-          if (a < na && l16 < ng && h[e] != 0.0) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * ng + l16, -h[e]);
-        }
       }
     }
     __syncthreads();

@@ -54,6 +54,8 @@ TINY = [
     dict(kind="conventional", species_table=((5, 9),), r_c=7.0, r_v=9.0, r_d=10.0, eps=1e-6),
     dict(kind="conventional", species_table=((4, 7), (6, 10)), species=[0, 1] * 4, r_c=7.0, r_v=9.0, r_d=10.0,
          eps=1e-4),
+    # blocks wider than one 16x16 matrix-core tile, next to narrow ones
+    dict(kind="primitive", species_table=((18, 21), (3, 5)), species=[0, 1], r_c=6.0, r_v=7.0, r_d=8.0, eps=1e-3),
 ]
 
 
@@ -158,3 +160,54 @@ def test_cfg3_eps1e4_full_vs_primitive():
     """512-atom supercell (4^3 conventional cells), 13 AO / 60 ABF, eps 1e-4: every Sigma block
     of the GPU build equals the oracle's primitive-cell block of the same atom pair."""
     _supercell_vs_primitive("cfg3", 1e-4, 1e-11)
+
+
+def _combine(ws):
+    """One batched workload from several single-cell workloads."""
+    import dataclasses
+    return dataclasses.replace(ws[0], cells=[w.cells[0] for w in ws], C=[w.C[0] for w in ws],
+                               V=[w.V[0] for w in ws], D=[w.D[0] for w in ws])
+
+
+def test_multicell_tiny():
+    """Several independent cells of different shapes and species in one launch: each cell's
+    Sigma equals the oracle of that cell alone."""
+    log("case multicell tiny")
+    parts = [hs.make_workload("tiny", kind="primitive", species_table=((2, 3), (3, 4)), species=[0, 1],
+                              r_c=8.0, r_v=6.0, r_d=9.0, seed=11),
+             hs.make_workload("tiny", kind="conventional", species_table=((5, 9),), r_c=7.0, r_v=9.0, r_d=10.0,
+                              eps=1e-6, seed=12),
+             hs.make_workload("tiny", kind="custom", lattice=np.eye(3) * 300.0,
+                              pos=[[0.0, 0.0, 0.0], [2.5, 1.0, -0.5]], species_table=((2, 3), (3, 2)),
+                              species=[0, 1], r_c=6.0, r_v=6.0, r_d=6.0, seed=13)]
+    w = _combine(parts)
+    w = w.__class__(**{**w.__dict__, "thresholds": parts[1].thresholds})
+    sig, e, st = gpu_build(w)
+    for c, p in enumerate(parts):
+        ref = oracle.run(p.cells[0], p.C[0], p.V[0], p.D[0], w.thresholds, n_threads=8)
+        check_close(sig[c], ref.sigma, label=f"multicell[{c}]")
+        assert abs(e[c] - oracle.energy(p.cells[0], p.D[0], ref.sigma)) <= 1e-11 * abs(e[c])
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_batched_cells_home_subset():
+    """48 cells of 1..3 x 1..3 x 1..3 conventional cells (8..216 atoms), two species (13 AO / 60 ABF
+    and 27 AO / 100 ABF) drawn per site, all built in one persistent launch with one seeded home
+    atom per cell; three seeded cells are checked against the oracle of that cell with the same
+    home atom (the other cells' items run in the same launch)."""
+    log("case cfg4")
+    w = hs.make_workload("cfg4")
+    rng = np.random.default_rng(2009)
+    home_local = [int(rng.integers(c.n_atoms)) for c in w.cells]
+    offs = np.cumsum([0] + [c.n_atoms for c in w.cells])
+    home = [int(offs[k] + a) for k, a in enumerate(home_local)]
+    t = time.time()
+    sig, e, st = gpu_build(w, home_subset=home)
+    log(f"cfg4 gpu {time.time() - t:.1f}s items {st['items']} units {[st[f'kept_s3_t{t}'] for t in (1, 2, 3, 4)]}")
+    checked = sorted(rng.choice(len(w.cells), size=3, replace=False).tolist())
+    for k in checked:
+        cell = w.cells[k]
+        t = time.time()
+        ref = oracle.run(cell, w.C[k], w.V[k], w.D[k], w.thresholds, home=[home_local[k]], n_threads=16)
+        log(f"cfg4 cell {k}: oracle {time.time() - t:.1f}s")
+        check_close(sig[k], ref.sigma, label=f"cfg4 cell {k} ({cell.n_atoms} atoms)")
