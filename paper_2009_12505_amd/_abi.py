@@ -18,7 +18,9 @@ SCREEN_ALL = 31
 SCHED_PLAN, SCHED_LPT, SCHED_MLP = 0, 1, 2
 
 EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "hfx_item_profile",
-            "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version"]
+            "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",
+            "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features"]
+ITEM_UNITS = 5
 
 
 class Species(ctypes.Structure):
@@ -102,6 +104,17 @@ def lib():
         L.hfx_last_error.argtypes = []
         L.hfx_abi_version.restype = ctypes.c_int32
         L.hfx_abi_version.argtypes = []
+        L.hfx_mlp_n_params.restype = ctypes.c_int64
+        L.hfx_mlp_n_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.hfx_mlp_predict.restype = ctypes.c_int
+        L.hfx_mlp_predict.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64, P, P]
+        L.hfx_mlp_loss_grad.restype = ctypes.c_int
+        L.hfx_mlp_loss_grad.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, P, P, P]
+        L.hfx_mlp_train.restype = ctypes.c_int
+        L.hfx_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_float, P, P]
+        L.hfx_item_features.restype = ctypes.c_int
+        L.hfx_item_features.argtypes = [P, P, P, P]
         _lib = L
     return _lib
 

@@ -80,7 +80,7 @@ struct DevPlan {
   unsigned long long *counters;  // see kCnt* below
   double *flops;                 // [0] Algorithm-3 count, [1] this kernel's useful count
   long long *item_cycles;        // per item (plan order)
-  int *item_units;               // per item x 4
+  int *item_units;               // per item x kItemUnits
 };
 
 enum {
@@ -94,6 +94,8 @@ enum {
   kCntPhase = 18,  // 6 entries: wall-clock ticks per phase, summed over items
   kCntN = 24
 };
+
+constexpr int kItemUnits = 5;  // per item: kept units of terms 1..4, alive G
 
 constexpr uint32_t kPre = 1u, kCsEri = 2u, kCs1 = 4u, kCs2 = 8u, kCs3 = 16u;
 

@@ -34,7 +34,6 @@ constexpr int NT = 512;
 constexpr int NW = NT / 64;
 constexpr int MAXNB = 160;
 constexpr int MAXN = 32;
-constexpr int kTileWords = 8;  // column-tile bitmask words of GEMM-R (up to 512 tiles)
 
 // v_mfma_f64_16x16x4f64 lane layout (gfx950): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; element e of the result holds D[l/16 + 4e][l%16].
@@ -1136,7 +1135,8 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       }
     if (tid < kCntN && L.cnt[tid]) atomicAdd(&P.counters[tid], L.cnt[tid]);
     if (tid < 2 && L.flops[tid] != 0.0) atomicAdd(&P.flops[tid], L.flops[tid]);
-    if (tid < 4) P.item_units[item * 4 + tid] = (int)L.cnt[kCntKept + 8 + tid];
+    if (tid < 4) P.item_units[item * kItemUnits + tid] = (int)L.cnt[kCntKept + 8 + tid];
+    if (tid == 4) P.item_units[item * kItemUnits + 4] = L.nGa;
     if (tid == 0) P.item_cycles[item] = wall_clock64() - t_start;
     __syncthreads();
   }

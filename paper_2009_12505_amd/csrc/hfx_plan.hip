@@ -46,6 +46,16 @@ hipError_t launch_dmax(const double *gD, const uint8_t *keepD, const long long *
                        hipStream_t s);
 hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, double *flops, hipStream_t s);
 hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s);
+hipError_t mlp_launch_predict(const float *P, int F, int H, const float *X, long long n, float *out, hipStream_t s);
+hipError_t mlp_launch_grad(const float *P, int F, int H, const float *X, const float *T, long long n, float *G,
+                           float *loss, hipStream_t s);
+hipError_t mlp_launch_adam(float *P, const float *G, float *m, float *v, int np, float lr, int step, hipStream_t s);
+hipError_t mlp_launch_features(const Item *items, const int *units, const int *c_start, const int *nao,
+                               const int *nabf, long long n, const float *mu, const float *sd, float *X,
+                               hipStream_t s);
+int64_t mlp_params(int F, int H);
+int mlp_max_h();
+int mlp_max_f();
 }  // namespace hfx
 
 using namespace hfx;
@@ -123,6 +133,12 @@ struct hfx_plan {
   int n_slots = 0, rows_cap = 0, cols_cap = 0, ld3 = 0;
   long long wave_off = 0, wave_doubles = 0, wg_off = 0;
   double *part = nullptr;  // energy partial sums
+  // learned scheduler
+  bool have_profile = false;
+  int mlp_f = 0, mlp_h = 0;
+  float *feat_musd = nullptr;  // normalisation for hfx_item_features
+  float *mlp_params_dev = nullptr, *mlp_mu = nullptr, *mlp_sd = nullptr, *mlp_X = nullptr, *mlp_y = nullptr;
+  std::vector<int32_t> lpt_order;
   int part_blocks = 1024;
   double *staging = nullptr;  // pinned host staging for D
   size_t staging_n = 0;
@@ -624,7 +640,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       (st = p->dalloc(&d_S, (size_t)p->sbase[n_cells])) || (st = p->dalloc(&d_gD, (size_t)p->nD)) ||
       (st = p->dalloc(&d_keepD, (size_t)p->nD)) || (st = p->upload(&d_items, p->items)) ||
       (st = p->upload(&d_order, ord32)) || (st = p->dalloc(&d_ticket, 1)) || (st = p->dalloc(&d_cnt, kCntN)) ||
-      (st = p->dalloc(&d_flops, 2)) || (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * 4)) ||
+      (st = p->dalloc(&d_flops, 2)) || (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * kItemUnits)) ||
       (st = p->dalloc(&d_scr, (size_t)p->n_slots * slot)) || (st = p->dalloc(&p->part, 2 * p->part_blocks)))
     return st;
   cstage.clear();
@@ -697,6 +713,32 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
                           p->d_row_dev, p->d_col_dev, p->dbase_dev};
     for (const void *q : must)
       if (!q) return fail(HFX_ERR_OOM, "internal: a device buffer of the plan was not allocated");
+  }
+  p->lpt_order = p->order;
+  if (p->scheduler == HFX_SCHED_MLP) {
+    FILE *fp = std::fopen(o.mlp_weights, "rb");
+    if (!fp) return fail(HFX_ERR_ARG, "cannot open mlp_weights '%s'", o.mlp_weights);
+    char magic[8];
+    int32_t fh[2];
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "HFXMLP01", 8) == 0 &&
+              std::fread(fh, sizeof(int32_t), 2, fp) == 2 && fh[0] == 8 && fh[1] >= 1 && fh[1] <= mlp_max_h();
+    std::vector<float> mu, sd, prm;
+    if (ok) {
+      mu.resize(fh[0]);
+      sd.resize(fh[0]);
+      prm.resize((size_t)mlp_params(fh[0], fh[1]));
+      ok = std::fread(mu.data(), sizeof(float), mu.size(), fp) == mu.size() &&
+           std::fread(sd.data(), sizeof(float), sd.size(), fp) == sd.size() &&
+           std::fread(prm.data(), sizeof(float), prm.size(), fp) == prm.size();
+    }
+    std::fclose(fp);
+    if (!ok) return fail(HFX_ERR_ARG, "mlp_weights '%s' is not a scheduler model file", o.mlp_weights);
+    p->mlp_f = fh[0];
+    p->mlp_h = fh[1];
+    if ((st = p->upload(&p->mlp_params_dev, prm)) || (st = p->upload(&p->mlp_mu, mu)) ||
+        (st = p->upload(&p->mlp_sd, sd)) || (st = p->dalloc(&p->mlp_X, (size_t)p->n_items * fh[0])) ||
+        (st = p->dalloc(&p->mlp_y, (size_t)p->n_items)))
+      return st;
   }
   // ---- plan-time kernels: C norms, CS-ERI factors, V norms
   HIPCHK(p, launch_cnorm(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_cn, p->stream));
@@ -780,10 +822,26 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
   HIPCHK(p, launch_dmax(P.gD, P.keepD, p->dbase_dev, p->gDmax_dev, p->n_cells, p->stream));
   HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
   HIPCHK(p, launch_reset(P.ticket, P.counters, P.flops, p->stream));
+  if (p->scheduler == HFX_SCHED_MLP && p->have_profile && p->n_items > 0) {
+    // learned costs from the previous build's per-item counters; longest predicted first
+    HIPCHK(p, mlp_launch_features(P.items, P.item_units, P.c_start, P.nao, P.nabf, p->n_items, p->mlp_mu, p->mlp_sd,
+                                  p->mlp_X, p->stream));
+    HIPCHK(p, mlp_launch_predict(p->mlp_params_dev, p->mlp_f, p->mlp_h, p->mlp_X, p->n_items, p->mlp_y, p->stream));
+    std::vector<float> pred(p->n_items);
+    HIPCHK(p, hipMemcpyAsync(pred.data(), p->mlp_y, pred.size() * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    std::vector<int32_t> ord(p->n_items);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return pred[x] > pred[y]; });
+    HIPCHK(p, hipMemcpyAsync(const_cast<int32_t *>(P.order), ord.data(), ord.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+  }
   HIPCHK(p, hipEventRecord(p->ev1, p->stream));
   if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles,
                                           p->wg_off, p->stream));
   HIPCHK(p, hipEventRecord(p->ev2, p->stream));
+  p->have_profile = true;
   for (int c = 0; c < p->n_cells; ++c) {
     const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
     if (n) HIPCHK(p, hipMemcpyAsync(sigma[c], P.Sbuf + p->sbase[c], n * sizeof(double), hipMemcpyDeviceToDevice,
@@ -856,10 +914,81 @@ hfx_status hfx_item_profile(hfx_plan *p, int64_t *n_items, int64_t *cycles, int6
     for (int64_t i = 0; i < p->n_items; ++i) cycles[i] = c[i];
   }
   if (units && p->n_items) {
-    std::vector<int> u(4 * p->n_items);
+    std::vector<int> u((size_t)kItemUnits * p->n_items);
     HIPCHK(p, hipMemcpy(u.data(), p->dp.item_units, u.size() * sizeof(int), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < u.size(); ++i) units[i] = u[i];
   }
+  return HFX_OK;
+}
+
+hfx_status hfx_item_features(hfx_plan *p, const float *mu, const float *sd, float *X) {
+  if (!p || !mu || !sd || !X) return fail(HFX_ERR_ARG, "NULL argument");
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  if (!p->have_profile) return fail(HFX_ERR_STATE, "item features need a completed build");
+  hfx_status st;
+  if (!p->feat_musd && (st = p->dalloc(&p->feat_musd, 16))) return st;
+  float musd[16];
+  std::memcpy(musd, mu, 8 * sizeof(float));
+  std::memcpy(musd + 8, sd, 8 * sizeof(float));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  HIPCHK(p, hipMemcpy(p->feat_musd, musd, sizeof(musd), hipMemcpyHostToDevice));
+  HIPCHK(p, mlp_launch_features(p->dp.items, p->dp.item_units, p->dp.c_start, p->dp.nao, p->dp.nabf, p->n_items,
+                                p->feat_musd, p->feat_musd + 8, X, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  return HFX_OK;
+}
+
+int64_t hfx_mlp_n_params(int32_t n_in, int32_t n_hidden) { return mlp_params(n_in, n_hidden); }
+
+static hfx_status mlp_check(int32_t n_in, int32_t n_hidden, const void *a, const void *b, int64_t n) {
+  if (n_in < 1 || n_in > mlp_max_f() || n_hidden < 1 || n_hidden > mlp_max_h())
+    return fail(HFX_ERR_ARG, "n_in must be 1..%d and n_hidden 1..%d", mlp_max_f(), mlp_max_h());
+  if (!a || !b || n < 0) return fail(HFX_ERR_ARG, "NULL argument or negative n");
+  return HFX_OK;
+}
+
+hfx_status hfx_mlp_predict(int32_t n_in, int32_t n_hidden, const float *params, const float *X, int64_t n, float *y,
+                           void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, params, X, n);
+  if (st) return st;
+  if (!y) return fail(HFX_ERR_ARG, "NULL output");
+  if (mlp_launch_predict(params, n_in, n_hidden, X, n, y, (hipStream_t)stream) != hipSuccess)
+    return fail(HFX_ERR_HIP, "predict launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return HFX_OK;
+}
+
+hfx_status hfx_mlp_loss_grad(int32_t n_in, int32_t n_hidden, const float *params, const float *X, const float *t,
+                             int64_t n, float *grad, float *loss, void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, params, X, n);
+  if (st) return st;
+  if (!t || !grad || !loss) return fail(HFX_ERR_ARG, "NULL argument");
+  if (mlp_launch_grad(params, n_in, n_hidden, X, t, n, grad, loss, (hipStream_t)stream) != hipSuccess)
+    return fail(HFX_ERR_HIP, "gradient launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return HFX_OK;
+}
+
+hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, float *params, const float *X, const float *t, int64_t n,
+                         int32_t epochs, float lr, float *loss_host, void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, params, X, n);
+  if (st) return st;
+  if (!t || epochs < 0 || !(lr > 0)) return fail(HFX_ERR_ARG, "bad targets, epochs or learning rate");
+  const int np = (int)mlp_params(n_in, n_hidden);
+  hipStream_t s = (hipStream_t)stream;
+  float *buf = nullptr;
+  if (hipMalloc(&buf, sizeof(float) * (3 * (size_t)np + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HFX_ERR_OOM, "optimizer state allocation failed");
+  }
+  float *G = buf, *m = buf + np, *v = buf + 2 * np, *loss = buf + 3 * np;
+  hipError_t e = hipMemsetAsync(m, 0, sizeof(float) * 2 * np, s);
+  for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+    e = mlp_launch_grad(params, n_in, n_hidden, X, t, n, G, loss, s);
+    if (e == hipSuccess && loss_host) e = hipMemcpyAsync(loss_host + ep, loss, sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = mlp_launch_adam(params, G, m, v, np, lr, ep + 1, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(HFX_ERR_HIP, "training failed: %s", hipGetErrorString(e));
   return HFX_OK;
 }
 

@@ -143,10 +143,21 @@ class Plan:
         del args
         return list(e)
 
+    def item_features(self, mu, sd):
+        """Scheduler features of every item from the last build (device float32 tensor [n_items, 8])."""
+        torch = self._torch
+        mu = np.ascontiguousarray(mu, np.float32)
+        sd = np.ascontiguousarray(sd, np.float32)
+        n = ctypes.c_int64()
+        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None))
+        X = torch.empty((n.value, 8), dtype=torch.float32, device="cuda")
+        A.check(A.lib().hfx_item_features(self._h, _ptr(mu), _ptr(sd), ctypes.c_void_p(X.data_ptr())))
+        return X
+
     def item_profile(self):
         n = ctypes.c_int64()
         A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None))
         cyc = np.zeros(n.value, np.int64)
-        units = np.zeros((n.value, 4), np.int64)
+        units = np.zeros((n.value, A.ITEM_UNITS), np.int64)
         A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), _ptr(cyc), _ptr(units)))
         return cyc, units

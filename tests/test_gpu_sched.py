@@ -1,0 +1,169 @@
+"""Learned scheduler: the MLP kernels against the FP64 reference, training on the GPU,
+and what the learned order gains over the static longest-first order on uneven cells."""
+import ctypes
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import hfx_synth as hs
+from oracle import mlp as ref
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@pytest.mark.parametrize("F,H,n", [(8, 32, 1000), (3, 5, 7), (8, 64, 4097), (16, 1, 1)])
+def test_mlp_forward_and_gradient_vs_fp64(F, H, n):
+    import torch
+    from paper_2009_12505_amd import lib
+    log(f"case mlp F={F} H={H} n={n}")
+    rng = np.random.default_rng(F * 1000 + H + n)
+    p = ref.init(F, H, seed=n) + rng.normal(0, 0.05, ref.n_params(F, H))
+    X = rng.normal(size=(n, F))
+    t = rng.normal(size=n)
+    # the reference sees the same FP32-rounded inputs
+    p32, X32, t32 = p.astype(np.float32), X.astype(np.float32), t.astype(np.float32)
+    P, Xd, Td = _dev(p32), _dev(X32), _dev(t32)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    g = torch.empty(ref.n_params(F, H), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib().hfx_mlp_n_params(F, H) == ref.n_params(F, H)
+    assert lib().hfx_mlp_predict(F, H, _vp(P), _vp(Xd), n, _vp(y), s) == 0
+    assert lib().hfx_mlp_loss_grad(F, H, _vp(P), _vp(Xd), _vp(Td), n, _vp(g), _vp(loss), s) == 0
+    torch.cuda.synchronize()
+    y_ref, _, _ = ref.forward(p32.astype(np.float64), X32, F, H)
+    L_ref, g_ref = ref.loss_grad(p32.astype(np.float64), X32, t32, F, H)
+    ey = np.max(np.abs(y.cpu().numpy() - y_ref))
+    eg = np.max(np.abs(g.cpu().numpy() - g_ref)) / np.max(np.abs(g_ref))
+    el = abs(float(loss.cpu()[0]) - L_ref) / L_ref
+    log(f"  max|dy|={ey:.2e} rel|dgrad|={eg:.2e} rel|dloss|={el:.2e}")
+    assert ey <= 2e-5 * max(1.0, np.max(np.abs(y_ref)))
+    assert eg <= 2e-5
+    assert el <= 2e-5
+
+
+def test_mlp_adam_first_step_and_training():
+    """Adam's bias-corrected first step moves each parameter by lr * sign(gradient); full-batch
+    training then fits a smooth target."""
+    import torch
+    from paper_2009_12505_amd import lib
+    F, H, n = 8, 32, 4096
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(n, F)).astype(np.float32)
+    t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] - 0.3 * X[:, 3]).astype(np.float32)
+    p0 = ref.init(F, H, seed=1).astype(np.float32)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    lr = 1e-3
+    P, Xd, Td = _dev(p0), _dev(X), _dev(t)
+    assert lib().hfx_mlp_train(F, H, _vp(P), _vp(Xd), _vp(Td), n, 1, ctypes.c_float(lr), None, s) == 0
+    _, g_ref = ref.loss_grad(p0.astype(np.float64), X, t, F, H)
+    step = P.cpu().numpy().astype(np.float64) - p0
+    big = np.abs(g_ref) > 1e-4
+    assert np.allclose(step[big], -lr * np.sign(g_ref[big]), rtol=1e-3, atol=1e-7)
+    P = _dev(p0)
+    L = np.zeros(800, np.float32)
+    t0 = time.time()
+    assert lib().hfx_mlp_train(F, H, _vp(P), _vp(Xd), _vp(Td), n, 800, ctypes.c_float(3e-3),
+                               L.ctypes.data_as(ctypes.c_void_p), s) == 0
+    log(f"800 epochs on {n} samples: {time.time() - t0:.2f}s, loss {L[0]:.4f} -> {L[-1]:.4f}")
+    assert L[-1] < 0.05 * L[0]
+    assert ref.loss(P.cpu().numpy().astype(np.float64), X, t, F, H) < 0.05 * L[0]
+
+
+def _spearman(a, b):
+    ra = np.argsort(np.argsort(a))
+    rb = np.argsort(np.argsort(b))
+    return float(np.corrcoef(ra, rb)[0, 1])
+
+
+@pytest.mark.timeout(900)
+def test_learned_order_on_uneven_cells(tmp_path):
+    """Uneven batched cells (48 cells of 8..216 atoms, two species): train the cost model on the
+    item ticks of builds over one set of home atoms, then order builds over another set.  Sigma is
+    unchanged; the learned costs rank items better than the static |N(A)||N(B)| cost, and the
+    build time of each order is reported."""
+    import torch
+    from paper_2009_12505_amd import SCHED_LPT, SCHED_MLP, SCHED_PLAN, Plan, sched
+    w = hs.make_workload("cfg4")
+    rng = np.random.default_rng(77)
+    offs = np.cumsum([0] + [c.n_atoms for c in w.cells])
+
+    def homes(k):
+        return sorted({int(offs[c] + a) for c in range(len(w.cells))
+                       for a in rng.choice(w.cells[c].n_atoms, size=min(k, w.cells[c].n_atoms), replace=False)})
+
+    h_train, h_test = homes(2), homes(2)
+    log(f"cfg4: {len(h_train)} training home atoms, {len(h_test)} test home atoms")
+    pl = Plan(w.cells, w.C, w.V, w.D, w.thresholds, scheduler=SCHED_LPT, home_subset=h_train)
+    samples = []
+    for _ in range(2):
+        pl.build(w.D, stats=True)
+        samples.append(sched.profile_samples(pl))
+    del pl
+    torch.cuda.empty_cache()
+    t0 = time.time()
+    model = sched.train(samples, hidden=32, epochs=1500, lr=3e-3)
+    log(f"trained on {sum(len(s[1]) for s in samples)} items in {time.time() - t0:.1f}s: "
+        f"loss {model.loss[0]:.3f} -> {model.loss[-1]:.3f}")
+    path = tmp_path / "sched.bin"
+    sched.save(model, path)
+    m2 = sched.load(path)
+    assert np.array_equal(m2.params, model.params)
+
+    def timed(plan, reps):
+        out = []
+        for _ in range(reps):
+            sig = plan.build(w.D, stats=True)
+            out.append(plan.last_stats["ms_main"])
+        torch.cuda.synchronize()
+        return out, sig
+
+    res = {}
+    for name, kind in (("plan", SCHED_PLAN), ("lpt", SCHED_LPT), ("mlp", SCHED_MLP)):
+        plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, scheduler=kind, home_subset=h_test,
+                    mlp_weights=path if kind == SCHED_MLP else None)
+        ms, sig = timed(plan, 4)  # the learned order starts with the second build
+        res[name] = (ms, [s.cpu().numpy() for s in sig])
+        if kind == SCHED_LPT:
+            # ranking quality on the test homes, labels from this plan's last build
+            X, tl = sched.profile_samples(plan)
+            cyc, units = plan.item_profile()
+        log(f"order {name}: main kernel ms per build {[round(x, 1) for x in ms]}")
+        del plan, sig
+        torch.cuda.empty_cache()
+    for c in range(len(w.cells)):
+        a, b = res["lpt"][1][c], res["mlp"][1][c]
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(a)), 1e-300)
+    pred = sched.predict(model, X)
+    nfng = np.exp(X[:, 5])
+    r_mlp, r_static = _spearman(pred, tl), _spearman(nfng, tl)
+    # a stronger hand-made cost: the kept units of the previous build, each unit of a term
+    # costing one C-block product, plus the G-side work of every alive G
+    kept = units[:, :4].sum(axis=1).astype(np.float64) + 4.0 * units[:, 4]
+    mk = {k: sched.list_schedule_makespan(cyc, np.argsort(-v, kind="stable"), 256) / 1e5
+          for k, v in (("static", nfng), ("units", kept), ("mlp", pred), ("measured", cyc.astype(np.float64)))}
+    log(f"Spearman(kept units, ticks) = {_spearman(kept, tl):.3f}; makespan with the kept-unit order "
+        f"{mk['units']:.1f} ms")
+    log(f"Spearman(pred, ticks) = {r_mlp:.3f}, Spearman(|N(A)||N(B)|, ticks) = {r_static:.3f}")
+    log(f"list-schedule makespan on 256 slots [ms]: static {mk['static']:.1f}, learned {mk['mlp']:.1f}, "
+        f"oracle order {mk['measured']:.1f}")
+    best = {k: min(v[0][1:]) for k, v in res.items()}
+    log(f"best main-kernel ms (builds 2..4): plan {best['plan']:.1f}, lpt {best['lpt']:.1f}, mlp {best['mlp']:.1f}")
+    assert r_mlp > r_static
+    assert mk["mlp"] <= mk["static"] * 1.001
