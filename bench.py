@@ -38,6 +38,40 @@ def cpu_baseline(eps: float, flops_per_atom_paper: float, n_threads: int):
                       "the 512-atom build is 512 such atoms", "units_sample": r.stats["units_formed"]}
 
 
+def progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the sources of the main kernel (its body and the shared device structures)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("hfx_kernels.hip", "hfx_internal.h"):
+        with open(os.path.join(ROOT, "paper_2009_12505_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(eps: float):
+    """HBM bytes per launch of the main kernel from the committed counter summary, if it was
+    taken on the current kernel source and this workload (else None)."""
+    path = os.path.join(ROOT, "profiles", f"k_main_cfg3_eps{eps:g}_hbm_bytes.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +81,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the build runs on a single MI355X; multi-GPU sharding is "
@@ -58,19 +94,32 @@ def main():
     from paper_2009_12505_amd import Plan
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_kernel_bytes_read": n * 8, "copy_kernel_bytes_written": n * 8, "launches": 3}),
+              flush=True)
+        return
     t0 = time.perf_counter()
     w = hs.make_workload("cfg3", eps=args.eps)
     t_gen = time.perf_counter() - t0
+    progress(f"inputs generated in {t_gen:.1f}s")
     t0 = time.perf_counter()
     plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
+    progress(f"plan created in {t_plan:.1f}s")
     # D resident in HBM before the timed region
     D = [hs.Blocks(b.row, b.col, b.R, b.off, torch.from_numpy(b.data).cuda(), "D") for b in w.D]
     sigma = plan.alloc_sigma()
     torch.cuda.synchronize()
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         plan.build(D, sigma, stats=True)
+        progress(f"warmup build {k}: {plan.last_stats['ms_main']:.1f} ms")
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -80,6 +129,7 @@ def main():
     for _ in range(args.steps):
         plan.build(D, sigma, stats=True)   # stats: HIP events around the main kernel on the plan stream
         ms_main.append(plan.last_stats["ms_main"])
+        progress(f"timed build {len(ms_main)}: {ms_main[-1]:.1f} ms")
     ev1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
@@ -102,7 +152,7 @@ def main():
                    "eps": args.eps, "n_atoms": n_atoms, "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": round(fl_alg / (ms_k / 1e3) / 1e12, 4), "peak": FP64_PEAK_TF,
                      "unit": "TFLOP/s", "frac": round(fl_alg / (ms_k / 1e3) / 1e12 / FP64_PEAK_TF, 4),
-                     "traffic": None, "kernel": "hfx::k_main", "kernel_ms": round(ms_k, 3),
+                     "traffic": measured_traffic(args.eps), "kernel": "hfx::k_main", "kernel_ms": round(ms_k, 3),
                      "flops_per_launch": fl_alg},
         "flops_paper_per_build": fl_paper, "flops_alg_per_build": fl_alg,
         "mfma_flops_issued": sum(st["mfma_flops"]),
