@@ -133,6 +133,10 @@ typedef struct {
   uint64_t max_device_bytes;  /* 0 = unlimited; else plan creation fails with HFX_ERR_OOM
                                  when its device footprint would exceed this               */
   int32_t n_slots;            /* persistent workgroups (0 = automatic)                      */
+  int32_t use_graph;          /* 1: hfx_build replays one captured HIP graph of the whole
+                                 device-side build (D gather, D screening, Sigma clear,
+                                 persistent kernel, Sigma copy-out); needs D on the device;
+                                 the graph is re-captured when the D or Sigma pointers change */
 } hfx_options;
 
 typedef struct {               /* filled by hfx_build when non-NULL (synchronises)          */

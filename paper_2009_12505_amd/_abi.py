@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("stages", ctypes.c_uint32), ("tier_tau", ctypes.c_double),
                 ("tier_tau_bf", ctypes.c_double), ("scheduler", ctypes.c_int32), ("mlp_weights", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p), ("home_subset", ctypes.c_void_p), ("n_home_subset", ctypes.c_int32),
-                ("max_device_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32)]
+                ("max_device_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class BuildStats(ctypes.Structure):

@@ -1416,12 +1416,19 @@ size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3) {
          (size_t)rows_cap * sizeof(long long);
 }
 
+hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3) {
+  const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
+  return hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+}
+
 hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
-                       long long wave_doubles, long long wg_off, hipStream_t s) {
+                       long long wave_doubles, long long wg_off, hipStream_t s, bool set_lds) {
   KParams kp{rows_cap, cols_cap, ld3, wave_off, wave_doubles, wg_off};
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
-  hipError_t e = hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
-  if (e != hipSuccess) return e;
+  if (set_lds) {
+    hipError_t e = main_set_lds(rows_cap, cols_cap, ld3);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_main, dim3(n_slots), dim3(NT), dyn, s, P, kp);
   return hipGetLastError();
 }

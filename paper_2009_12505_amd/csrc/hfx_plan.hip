@@ -21,7 +21,8 @@
 
 namespace hfx {
 hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
-                       long long wave_doubles, long long wg_off, hipStream_t s);
+                       long long wave_doubles, long long wg_off, hipStream_t s, bool set_lds);
+hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3);
 size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3);
 hipError_t launch_ctrans(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
                          const int *nao, const int *nabf, int nC, double *CT, hipStream_t s);
@@ -143,8 +144,27 @@ struct hfx_plan {
   double *staging = nullptr;  // pinned host staging for D
   size_t staging_n = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  // graph mode: one captured graph of the device-side build, valid for the pointers in gkey
+  bool use_graph = false;
+  hipStream_t gstream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t gev_in = nullptr, gev_out = nullptr;
+  std::vector<const void *> gkey;
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    gkey.clear();
+  }
 
   ~hfx_plan() {
+    drop_graph();
+    if (gstream) (void)hipStreamDestroy(gstream);
+    if (gev_in) (void)hipEventDestroy(gev_in);
+    if (gev_out) (void)hipEventDestroy(gev_out);
     for (void *p : allocs) (void)hipFree(p);
     if (staging) (void)hipHostFree(staging);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -748,6 +768,12 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   HIPCHK(p, hipEventCreate(&p->ev0));
   HIPCHK(p, hipEventCreate(&p->ev1));
   HIPCHK(p, hipEventCreate(&p->ev2));
+  p->use_graph = o.use_graph != 0;
+  if (p->use_graph) {
+    HIPCHK(p, hipStreamCreateWithFlags(&p->gstream, hipStreamNonBlocking));
+    HIPCHK(p, hipEventCreateWithFlags(&p->gev_in, hipEventDisableTiming));
+    HIPCHK(p, hipEventCreateWithFlags(&p->gev_out, hipEventDisableTiming));
+  }
   HIPCHK(p, hipStreamSynchronize(p->stream));
   *out = plan.release();
   return HFX_OK;
@@ -767,7 +793,7 @@ hfx_status hfx_sigma_layout(const hfx_plan *p, int32_t cell, hfx_blocks *layout,
   return HFX_OK;
 }
 
-static hfx_status stage_d(hfx_plan *p, const hfx_blocks *D) {
+static hfx_status check_d(hfx_plan *p, const hfx_blocks *D) {
   if (!D) return fail(HFX_ERR_ARG, "D is NULL");
   for (int c = 0; c < p->n_cells; ++c) {
     const hfx_blocks &d = D[c];
@@ -781,6 +807,15 @@ static hfx_status stage_d(hfx_plan *p, const hfx_blocks *D) {
                   std::memcmp(d.col, p->d_col[c].data(), nb * sizeof(int32_t)) != 0 ||
                   std::memcmp(d.R, p->d_R[c].data(), 3 * nb * sizeof(int32_t)) != 0))
       return fail(HFX_ERR_STATE, "cell %d: D block structure differs from the plan's pattern", c);
+  }
+  return HFX_OK;
+}
+
+// copy D into the plan's compact layout on the plan stream (device D: one gather kernel per cell)
+static hfx_status enqueue_d(hfx_plan *p, const hfx_blocks *D) {
+  for (int c = 0; c < p->n_cells; ++c) {
+    const hfx_blocks &d = D[c];
+    const int64_t nb = (int64_t)p->d_row[c].size();
     if (nb == 0) continue;
     if (d.on_device) {
       HIPCHK(p, launch_dgather(d.data, p->d_inoff_dev[c], p->dp.d_off, (int)nb, p->dbase[c],
@@ -805,23 +840,83 @@ static hfx_status stage_d(hfx_plan *p, const hfx_blocks *D) {
   return HFX_OK;
 }
 
-hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx_build_stats *stats) {
-  if (!p) return fail(HFX_ERR_ARG, "plan is NULL");
-  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
-  if (!sigma) return fail(HFX_ERR_ARG, "sigma is NULL");
-  for (int c = 0; c < p->n_cells; ++c)
-    if (!sigma[c] && p->sbase[c + 1] > p->sbase[c]) return fail(HFX_ERR_ARG, "sigma[%d] is NULL", c);
-  hfx_status st = stage_d(p, D);
-  if (st) return st;
+static hfx_status stage_d(hfx_plan *p, const hfx_blocks *D) {
+  hfx_status st = check_d(p, D);
+  return st ? st : enqueue_d(p, D);
+}
+
+// the device-side build after D is staged: D screening, Sigma clear, the persistent kernel,
+// Sigma copy-out; `eager` adds the timing events and sets the kernel's LDS attribute
+static hfx_status enqueue_core(hfx_plan *p, double *const *sigma, bool eager) {
   DevPlan &P = p->dp;
   const long long ntot = p->sbase[p->n_cells];
-  HIPCHK(p, hipEventRecord(p->ev0, p->stream));
   HIPCHK(p, launch_dprep(P.Dbuf, P.d_off, p->d_row_dev, p->d_col_dev, P.nao, (int)p->nD, p->th.eps_D,
                          (p->stages & HFX_SCREEN_PRE) ? 1 : 0, const_cast<double *>(P.gD),
                          const_cast<uint8_t *>(P.keepD), p->stream));
   HIPCHK(p, launch_dmax(P.gD, P.keepD, p->dbase_dev, p->gDmax_dev, p->n_cells, p->stream));
   HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
   HIPCHK(p, launch_reset(P.ticket, P.counters, P.flops, p->stream));
+  if (eager) HIPCHK(p, hipEventRecord(p->ev1, p->stream));
+  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles,
+                                          p->wg_off, p->stream, eager));
+  if (eager) HIPCHK(p, hipEventRecord(p->ev2, p->stream));
+  for (int c = 0; c < p->n_cells; ++c) {
+    const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
+    if (n) HIPCHK(p, hipMemcpyAsync(sigma[c], P.Sbuf + p->sbase[c], n * sizeof(double), hipMemcpyDeviceToDevice,
+                                    p->stream));
+  }
+  return HFX_OK;
+}
+
+// graph mode: capture D staging + enqueue_core once on the plan's own stream, replay it
+static hfx_status graph_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma) {
+  std::vector<const void *> key;
+  for (int c = 0; c < p->n_cells; ++c) {
+    if (!p->d_row[c].empty() && !D[c].on_device)
+      return fail(HFX_ERR_ARG, "graph mode needs D in device memory (cell %d is on the host)", c);
+    key.push_back(D[c].data);
+    key.push_back(sigma[c]);
+  }
+  if (!p->gexec || key != p->gkey) {
+    p->drop_graph();
+    HIPCHK(p, main_set_lds(p->rows_cap, p->cols_cap, p->ld3));
+    hipStream_t user = p->stream;
+    p->stream = p->gstream;
+    HIPCHK(p, hipStreamBeginCapture(p->gstream, hipStreamCaptureModeThreadLocal));
+    hfx_status st = enqueue_d(p, D);
+    if (!st) st = enqueue_core(p, sigma, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->gstream, &g);
+    p->stream = user;
+    if (st || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return st ? st : p->hip_fail("hipStreamEndCapture");
+    }
+    p->graph = g;
+    HIPCHK(p, hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+    p->gkey = key;
+  }
+  // no separate kernel timing inside the graph: ev1 = ev0
+  HIPCHK(p, hipEventRecord(p->ev0, p->stream));
+  HIPCHK(p, hipEventRecord(p->ev1, p->stream));
+  HIPCHK(p, hipEventRecord(p->gev_in, p->stream));
+  HIPCHK(p, hipStreamWaitEvent(p->gstream, p->gev_in, 0));
+  HIPCHK(p, hipGraphLaunch(p->gexec, p->gstream));
+  HIPCHK(p, hipEventRecord(p->gev_out, p->gstream));
+  HIPCHK(p, hipStreamWaitEvent(p->stream, p->gev_out, 0));
+  HIPCHK(p, hipEventRecord(p->ev2, p->stream));
+  return HFX_OK;
+}
+
+hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx_build_stats *stats) {
+  if (!p) return fail(HFX_ERR_ARG, "plan is NULL");
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  if (!sigma) return fail(HFX_ERR_ARG, "sigma is NULL");
+  for (int c = 0; c < p->n_cells; ++c)
+    if (!sigma[c] && p->sbase[c + 1] > p->sbase[c]) return fail(HFX_ERR_ARG, "sigma[%d] is NULL", c);
+  hfx_status st = check_d(p, D);
+  if (st) return st;
+  DevPlan &P = p->dp;
   if (p->scheduler == HFX_SCHED_MLP && p->have_profile && p->n_items > 0) {
     // learned costs from the previous build's per-item counters; longest predicted first
     HIPCHK(p, mlp_launch_features(P.items, P.item_units, P.c_start, P.nao, P.nabf, p->n_items, p->mlp_mu, p->mlp_sd,
@@ -837,16 +932,13 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
                              hipMemcpyHostToDevice, p->stream));
     HIPCHK(p, hipStreamSynchronize(p->stream));
   }
-  HIPCHK(p, hipEventRecord(p->ev1, p->stream));
-  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles,
-                                          p->wg_off, p->stream));
-  HIPCHK(p, hipEventRecord(p->ev2, p->stream));
-  p->have_profile = true;
-  for (int c = 0; c < p->n_cells; ++c) {
-    const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
-    if (n) HIPCHK(p, hipMemcpyAsync(sigma[c], P.Sbuf + p->sbase[c], n * sizeof(double), hipMemcpyDeviceToDevice,
-                                    p->stream));
+  if (p->use_graph) {
+    if ((st = graph_build(p, D, sigma))) return st;
+  } else {
+    HIPCHK(p, hipEventRecord(p->ev0, p->stream));
+    if ((st = enqueue_d(p, D)) || (st = enqueue_core(p, sigma, true))) return st;
   }
+  p->have_profile = true;
   if (stats) {
     HIPCHK(p, hipStreamSynchronize(p->stream));
     unsigned long long cnt[kCntN];
