@@ -157,6 +157,7 @@ typedef struct {               /* filled by hfx_build when non-NULL (synchronise
   double phase_share[6];       /* share of the summed per-item time spent in: screening,
                                   Y = VC and the G-side products, stage-2/3 masks, terms 3+4,
                                   terms 1+2, item set-up                                     */
+  double mfma_flops_fp32;      /* part of mfma_flops issued on the FP32 matrix cores         */
 } hfx_build_stats;
 
 typedef struct hfx_plan hfx_plan;

@@ -57,13 +57,13 @@ class BuildStats(ctypes.Structure):
                 ("flops_contract", ctypes.c_double), ("flops_paper", ctypes.c_double),
                 ("flops_tier", ctypes.c_double * 3), ("mfma_flops", ctypes.c_double * 3),
                 ("ms_total", ctypes.c_double), ("ms_main", ctypes.c_double),
-                ("phase_share", ctypes.c_double * 6)]
+                ("phase_share", ctypes.c_double * 6), ("mfma_flops_fp32", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {"candidates": self.candidates, "kept_cs_eri": self.kept_cs_eri, "items": self.items,
              "g_alive": self.g_alive, "flops_contract": self.flops_contract, "flops_paper": self.flops_paper,
              "flops_tier": list(self.flops_tier), "mfma_flops": list(self.mfma_flops),
-             "ms_total": self.ms_total, "ms_main": self.ms_main,
+             "ms_total": self.ms_total, "ms_main": self.ms_main, "mfma_flops_fp32": self.mfma_flops_fp32,
              "phase_share": dict(zip(["screen", "gside", "masks", "gemm_r", "gemm_l", "setup"],
                                      [round(x, 4) for x in self.phase_share]))}
         for s in range(3):

@@ -43,6 +43,7 @@ struct DevPlan {
   // kept C blocks, grouped by row atom (c_start), sorted by distance within a row
   const double *Cbuf;
   const double *CTbuf;  // same blocks, each transposed to [n_ao(col)][n_abf(row) * n_ao(row)]
+  const float *C32, *CT32;  // FP32 copies of Cbuf and CTbuf (same offsets) for FP32 block products
   const long long *c_off;
   const int32_t *c_col, *c_R;
   const CNorm *c_norm;
@@ -92,7 +93,9 @@ enum {
   kCntMfmaL = 16,  // MFMA instructions issued, GEMM-L
   kCntMfmaY = 17,
   kCntPhase = 18,  // 6 entries: wall-clock ticks per phase, summed over items
-  kCntN = 24
+  kCntMfmaR32 = 24,  // FP32 MFMA instructions issued, GEMM-R
+  kCntMfmaL32 = 25,  // FP32 MFMA instructions issued, GEMM-L
+  kCntN = 26
 };
 
 constexpr int kItemUnits = 5;  // per item: kept units of terms 1..4, alive G

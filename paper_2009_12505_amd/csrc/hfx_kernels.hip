@@ -41,6 +41,14 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// v_mfma_f32_16x16x4f32 lane layout (gfx950): operands as for the FP64 form (lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]), but element e of the result holds D[4(l/16) + e][l%16].
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 // D block id of (row, col, R) for two atoms of one cell, given the cell's table base and size
 __device__ __forceinline__ int lookup_local(const DevPlan &P, int tbase, int n, int lrow, int lcol, int32_t R) {
   const int t = tbase + lrow * n + lcol;
@@ -98,6 +106,7 @@ struct ItemLds {
   double sq[2 * MAXN];
   // GEMM block bookkeeping
   unsigned blk_act;
+  unsigned blk_ub;  // largest stage-2 bound (float bits) of the kept units of the current block
   int t1any, kc, nsel;
   unsigned long long t2any;
   int fpos[MAXNB];
@@ -114,6 +123,9 @@ struct KParams {
   long long wave_off;      // offset (doubles) of the per-wave scratch regions in a slot
   long long wave_doubles;  // size of one per-wave region
   long long wg_off;        // offset (doubles) of the workgroup region (GEMM-L panel, P block)
+  long long ub_off;        // offset (doubles) of the per-(F,G) unit bounds used by the precision tiers
+  int tier;                // 0: FP64 block products; 1: FP32 for blocks whose bound <= tau; 2: all FP32
+  float tau;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -353,7 +365,7 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
 // ---------------------------------------------------------------------------------------------
 // masks: stages 2 and 3 for the stage-1 survivors of alive G's
 __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, uint8_t *mask, double *E2,
-                            double *wreg) {
+                            double *wreg, float *ub) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int nb = L.nb, nF = L.nF, nGa = L.nGa, nG = L.nG;
   const double eps = P.eps_mat;
@@ -384,7 +396,10 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
     const int j = L.a_j[jj];
     const int q = i * nG + j;
     uint8_t bits = mask[q];
-    if (!(bits & 15)) continue;
+    if (!(bits & 15)) {
+      if (ub) ub[2 * p] = ub[2 * p + 1] = 0.0f;
+      continue;
+    }
     if (bits & kT1) {
       if (!use2 || L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]] > eps) {
         ++c2[0];
@@ -426,6 +441,16 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       if (!keep) bits &= ~kT4;
     }
     mask[q] = bits;
+    if (ub) {
+      // stage-2 bounds of the surviving units, per GEMM: [0] terms 1, 2; [1] terms 3, 4
+      float bl = 0.0f, br = 0.0f;
+      if (bits & kT1) bl = fmaxf(bl, (float)(L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]]));
+      if (bits & kT2) bl = fmaxf(bl, (float)(L.f_gA[i] * L.a_Yg[jj] * P.gD[L.f_dFB[i]]));
+      if (bits & kT3) br = fmaxf(br, (float)(L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]]));
+      if (bits & kT4) br = fmaxf(br, (float)(L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB]));
+      ub[2 * p] = bl;
+      ub[2 * p + 1] = br;
+    }
   }
   __syncthreads();
   if (use3) {
@@ -580,7 +605,7 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned 
     if (more) fetch(k0 + BK);
     if (act) {
       const double *a = As + st * BK * BM, *b = Bs + st * BK * BN;
-#pragma unroll
+#pragma unroll 2
       for (int s = 0; s < BK / 4; ++s) {
         const int kr = 4 * s + kk;
         const double av = a[kr * BM + wave * 16 + l16];
@@ -593,6 +618,64 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned 
     __syncthreads();
     st ^= 1;
   }
+}
+
+// The same block product on the FP32 matrix cores (v_mfma_f32_16x16x4f32), same chunking:
+// operands are fetched as (or converted to) FP32, so the stages and the A operand traffic
+// are half those of the FP64 form and each MFMA takes half the matrix-core time.
+template <class AAt, class BAt>
+__device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, unsigned act, float *As, float *Bs,
+                                              f4 (&acc)[4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
+  const int ar = tid & (BM - 1), akq = (tid >> 7) << 2;
+  const int bc = tid & (BN - 1), bk = tid >> 6;
+  float ra[4], rb[2];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0f;
+    rb[0] = k0 + bk < K ? b_at(k0 + bk) : 0.0f;
+    rb[1] = k0 + bk + 8 < K ? b_at(k0 + bk + 8) : 0.0f;
+  };
+  auto stash = [&](int st) {
+    float *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = ra[s];
+    b[bk * BN + bc] = rb[0];
+    b[(bk + 8) * BN + bc] = rb[1];
+  };
+  __syncthreads();  // the previous user of the stages is done
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int st = 0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) fetch(k0 + BK);
+    if (act) {
+      const float *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+#pragma unroll 2
+      for (int s = 0; s < BK / 4; ++s) {
+        const int kr = 4 * s + kk;
+        const float av = a[kr * BM + wave * 16 + l16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (act & (1u << v)) acc[v] = mfma32(av, b[kr * BN + v * 16 + l16], acc[v]);
+      }
+    }
+    if (more) stash(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+}
+
+// largest recorded bound over the alive G's whose columns meet [c_lo, c_hi), for row F_i
+__device__ __forceinline__ float cols_ub(const ItemLds &L, const float *ub, const short *col2jj, int i, int c_lo,
+                                         int c_hi, int which) {
+  float m = 0.0f;
+  if (c_lo >= c_hi) return m;
+  const int jj0 = col2jj[c_lo], jj1 = col2jj[c_hi - 1];
+  for (int jj = jj0; jj <= jj1; ++jj) m = fmaxf(m, ub[2 * (i * L.nGa + jj) + which]);
+  return m;
 }
 
 // which of the four 16-column tiles of [c_lo, c_lo+64) hold a half (g or b) of some alive G
@@ -618,11 +701,11 @@ __device__ __forceinline__ bool tile_has(const ItemLds &L, const uint8_t *mask, 
 // 128 x 64 blocks in row-block-major order; a block whose 32 tiles hold no kept unit is skipped.
 __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
                              const uint8_t *row2i, const short *col2jj, double *As, double *Bs, double *acc3,
-                             int ld3) {
+                             int ld3, const float *ub, int tier, float tau) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int K = L.PA * L.na, nb = L.nb;
   const int nrb = (L.MR + BM - 1) / BM, ncb = (L.NR + BN - 1) / BN;
-  unsigned long long nmfma = 0;
+  unsigned long long nmfma = 0, nmfma32 = 0;
   for (int rb = 0; rb < nrb; ++rb) {
     for (int q = lane; q < 16 * ld3; q += 64) acc3[q] = 0.0;
     bool any3 = false;
@@ -630,23 +713,31 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
     const int r = rb * BM + (tid & (BM - 1));
     const bool rok = r < L.MR;
     const int ia = rok ? row2i[r] : 0;
-    const double *Ab = P.Cbuf + L.f_coff[ia] + (rok ? r - L.f_row0[ia] : 0);
+    const long long a_off = L.f_coff[ia] + (rok ? r - L.f_row0[ia] : 0);
+    const double *Ab = P.Cbuf + a_off;
+    const float *Ab32 = tier ? P.C32 + a_off : nullptr;
     const int As_ = L.f_n[ia];
     for (int cb = 0; cb < ncb; ++cb) {
-      if (tid == 0) L.blk_act = 0;
+      if (tid == 0) {
+        L.blk_act = 0;
+        L.blk_ub = 0u;
+      }
       __syncthreads();
       {
         const int sidx = tid >> 4, wr = sidx >> 2, ct = sidx & 3;
         const int rr = rb * BM + wr * 16 + (tid & 15);
         if (rr < L.MR) {
-          const int c_lo = cb * BN + ct * 16;
-          if (tile_has(L, mask, col2jj, row2i[rr], c_lo, min(c_lo + 16, L.NR), kT4, kT3))
+          const int c_lo = cb * BN + ct * 16, c_hi = min(c_lo + 16, L.NR);
+          if (tile_has(L, mask, col2jj, row2i[rr], c_lo, c_hi, kT4, kT3)) {
             atomicOr(&L.blk_act, 1u << sidx);
+            if (tier == 1) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, row2i[rr], c_lo, c_hi, 1)));
+          }
         }
       }
       __syncthreads();
       const unsigned act_all = L.blk_act;
       if (!act_all) continue;
+      const bool fp32 = tier == 2 || (tier == 1 && __uint_as_float(L.blk_ub) <= tau);
       const unsigned act = (act_all >> (4 * wave)) & 15u;
       const int c = cb * BN + (tid & (BN - 1));
       const bool cok = c < L.NR;
@@ -664,12 +755,27 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
         }
       }
       d4 acc[4];
+      if (fp32) {
+        f4 a32[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
-      wg_block_mm(
-          K, [&](int k) { return rok ? Ab[(long long)k * As_] : 0.0; },
-          [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, As, Bs, acc);
-      nmfma += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
+        for (int v = 0; v < 4; ++v) a32[v] = f4{0, 0, 0, 0};
+        wg_block_mm32(
+            K, [&](int k) { return rok ? Ab32[(long long)k * As_] : 0.0f; },
+            [&](int k) { return cok ? (float)Bb[(long long)k * Bstr] : 0.0f; }, act, reinterpret_cast<float *>(As),
+            reinterpret_cast<float *>(Bs), a32);
+        nmfma32 += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[v][e] = (double)a32[v][e];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
+        wg_block_mm(
+            K, [&](int k) { return rok ? Ab[(long long)k * As_] : 0.0; },
+            [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, As, Bs, acc);
+        nmfma += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
+      }
       // epilogue of this wave's tiles
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -679,7 +785,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
         const int jj = col2jj[cc0], j = L.a_j[jj];
         const int cc = cc0 - L.a_col0[jj], ng = L.g_n[j];
         for (int e = 0; e < 4; ++e) {
-          const int rl = kk + 4 * e;
+          const int rl = fp32 ? 4 * kk + e : kk + 4 * e;  // result row of element e (MFMA form)
           const int rr = rb * BM + wave * 16 + rl;
           if (rr >= L.MR) continue;
           const int i = row2i[rr], f = rr - L.f_row0[i];
@@ -709,6 +815,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
     }
   }
   if (lane == 0 && nmfma) atomicAdd(&L.cnt[kCntMfmaR], nmfma);
+  if (lane == 0 && nmfma32) atomicAdd(&L.cnt[kCntMfmaR32], nmfma32);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -722,20 +829,22 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 // C read from the per-block transposed copy, then contracted with Y on the matrix cores.
 __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
                              const short *col2jj, double *As, double *Bs, double *wg, int rows_cap,
-                             long long *kaddr /* LDS [rows_cap] */) {
+                             long long *kaddr /* LDS [rows_cap] */, const float *ub, int tier, float tau) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int M = L.PA * L.na, na = L.na, nb = L.nb, nF = L.nF, PA = L.PA;
   const int ncb = (L.NR + BN - 1) / BN, nrb = (M + BM - 1) / BM;
   double *panel = wg;                                   // [rows_cap][64]
   double *Pb = panel + (long long)rows_cap * BN;        // [M][64]
   const double *CT = P.CTbuf;
-  unsigned long long nmfma = 0;
+  const float *CT32 = P.CT32;
+  unsigned long long nmfma = 0, nmfma32 = 0;
   for (int cb = 0; cb < ncb; ++cb) {
     const int c0 = cb * BN, c1 = min(c0 + BN, L.NR);
     const int jj0 = col2jj[c0], jj1 = col2jj[c1 - 1];
     // F set of the block, targets with work, active column tiles
     if (tid == 0) {
       L.blk_act = 0;
+      L.blk_ub = 0u;
       L.t1any = 0;
       L.t2any = 0ull;
     }
@@ -756,14 +865,17 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
       L.fpos[i] = hit ? 1 : 0;
       if (t1) L.t1any = 1;
       if (t2) atomicOr(&L.t2any, t2);
-      if (hit)
+      if (hit) {
         for (int ct = 0; ct < 4; ++ct) {
           const int cl = c0 + ct * 16;
           if (tile_has(L, mask, col2jj, i, cl, min(cl + 16, c1), kT1, kT2)) atomicOr(&L.blk_act, 1u << ct);
         }
+        if (tier == 1) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, i, c0, c1, 0)));
+      }
     }
     __syncthreads();
     if (!L.blk_act) continue;
+    const bool fp32 = tier == 2 || (tier == 1 && __uint_as_float(L.blk_ub) <= tau);
     if (tid == 0) {
       int kc = 0, m = 0;
       for (int i = 0; i < nF; ++i)
@@ -820,22 +932,41 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
       const bool rok = r < M;
       const int bcl = tid & (BN - 1);
       d4 acc[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
       const unsigned act = (rb * BM + wave * 16 < M) ? colact : 0u;
-      wg_block_mm(
-          Kc,
-          [&](int k) {
-            const long long ka = kaddr[k];
-            return (rok && ka >= 0) ? CT[ka + r] : 0.0;
-          },
-          [&](int k) { return panel[(long long)k * BN + bcl]; }, act, As, Bs, acc);
-      nmfma += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
+      if (fp32) {
+        f4 a32[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a32[v] = f4{0, 0, 0, 0};
+        wg_block_mm32(
+            Kc,
+            [&](int k) {
+              const long long ka = kaddr[k];
+              return (rok && ka >= 0) ? CT32[ka + r] : 0.0f;
+            },
+            [&](int k) { return (float)panel[(long long)k * BN + bcl]; }, act, reinterpret_cast<float *>(As),
+            reinterpret_cast<float *>(Bs), a32);
+        nmfma32 += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[v][e] = (double)a32[v][e];
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
+        wg_block_mm(
+            Kc,
+            [&](int k) {
+              const long long ka = kaddr[k];
+              return (rok && ka >= 0) ? CT[ka + r] : 0.0;
+            },
+            [&](int k) { return panel[(long long)k * BN + bcl]; }, act, As, Bs, acc);
+        nmfma += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = rb * BM + wave * 16 + kk + 4 * e;
+          const int row = rb * BM + wave * 16 + (fp32 ? 4 * kk + e : kk + 4 * e);  // MFMA result row
           if (row < M) Pb[(long long)row * BN + v * 16 + l16] = (act & (1u << v)) ? acc[v][e] : 0.0;
         }
     }
@@ -903,6 +1034,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
     __syncthreads();
   }
   if (lane == 0 && nmfma) atomicAdd(&L.cnt[kCntMfmaL], nmfma);
+  if (lane == 0 && nmfma32) atomicAdd(&L.cnt[kCntMfmaL32], nmfma32);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1065,7 +1197,8 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       __syncthreads();
     }
     tick(1);
-    phase_masks(P, L, slot, dfg, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles);
+    float *ub = kp.tier == 1 ? reinterpret_cast<float *>(slot + kp.ub_off) : nullptr;
+    phase_masks(P, L, slot, dfg, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
       int lo = 0, hi = L.nF - 1;
@@ -1119,10 +1252,12 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     __syncthreads();
     tick(2);
     if (L.nGa > 0) {
-      phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3);
+      phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
+                   kp.tier, kp.tau);
       __syncthreads();
       tick(3);
-      phase_gemm_l(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr);
+      phase_gemm_l(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr, ub, kp.tier,
+                   kp.tau);
     }
     __syncthreads();
     tick(4);
@@ -1310,6 +1445,12 @@ __global__ __launch_bounds__(256) void k_ctrans(const double *__restrict__ Cbuf,
   }
 }
 
+// plan-time: FP32 copy of an FP64 buffer (operands of the FP32 block products)
+__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, long long n) {
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+    dst[q] = (float)src[q];
+}
+
 // per build: gather D blocks from the caller layout into the compact layout
 __global__ void k_dgather(const double *__restrict__ src, const long long *__restrict__ src_off,
                           const long long *__restrict__ dst_off, int nD, long long base, double *__restrict__ dst) {
@@ -1416,14 +1557,20 @@ size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3) {
          (size_t)rows_cap * sizeof(long long);
 }
 
+hipError_t launch_to_f32(const double *src, float *dst, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3) {
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
   return hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
 }
 
 hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
-                       long long wave_doubles, long long wg_off, hipStream_t s, bool set_lds) {
-  KParams kp{rows_cap, cols_cap, ld3, wave_off, wave_doubles, wg_off};
+                       long long wave_doubles, long long wg_off, long long ub_off, int tier, float tau, hipStream_t s,
+                       bool set_lds) {
+  KParams kp{rows_cap, cols_cap, ld3, wave_off, wave_doubles, wg_off, ub_off, tier, tau};
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
   if (set_lds) {
     hipError_t e = main_set_lds(rows_cap, cols_cap, ld3);

@@ -21,8 +21,10 @@
 
 namespace hfx {
 hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
-                       long long wave_doubles, long long wg_off, hipStream_t s, bool set_lds);
+                       long long wave_doubles, long long wg_off, long long ub_off, int tier, float tau, hipStream_t s,
+                       bool set_lds);
 hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3);
+hipError_t launch_to_f32(const double *src, float *dst, long long n, hipStream_t s);
 size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3);
 hipError_t launch_ctrans(const double *Cbuf, const long long *c_off, const int *c_row, const int *c_col,
                          const int *nao, const int *nabf, int nC, double *CT, hipStream_t s);
@@ -132,7 +134,9 @@ struct hfx_plan {
 
   DevPlan dp{};
   int n_slots = 0, rows_cap = 0, cols_cap = 0, ld3 = 0;
-  long long wave_off = 0, wave_doubles = 0, wg_off = 0;
+  long long wave_off = 0, wave_doubles = 0, wg_off = 0, ub_off = 0;
+  int tier = 0;       // 0: FP64 block products; 1: bound-tiered FP32; 2: all FP32
+  float tau = 0.0f;
   double *part = nullptr;  // energy partial sums
   // learned scheduler
   bool have_profile = false;
@@ -277,8 +281,12 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     if (!std::isfinite(e) || e < 0) return fail(HFX_ERR_ARG, "thresholds must be finite and >= 0");
   hfx_options o{};
   if (opt) o = *opt;
-  if (o.precision != HFX_PREC_FP64)
-    return fail(HFX_ERR_UNSUPPORTED, "precision %d is not available in this build", o.precision);
+  if (o.precision == HFX_PREC_BF16X3)
+    return fail(HFX_ERR_UNSUPPORTED, "split-BF16x3 block products are not available in this build");
+  if (o.precision < HFX_PREC_FP64 || o.precision > HFX_PREC_TIERED)
+    return fail(HFX_ERR_ARG, "unknown precision %d", o.precision);
+  if (o.precision == HFX_PREC_TIERED && !(o.tier_tau >= 0 && std::isfinite(o.tier_tau)))
+    return fail(HFX_ERR_ARG, "tier_tau must be finite and >= 0");
   if (o.scheduler < HFX_SCHED_PLAN || o.scheduler > HFX_SCHED_MLP)
     return fail(HFX_ERR_ARG, "unknown scheduler %d", o.scheduler);
   if (o.scheduler == HFX_SCHED_MLP && !o.mlp_weights)
@@ -290,6 +298,8 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   p->th = *th;
   p->stages = o.stages ? o.stages : HFX_SCREEN_ALL;
   p->precision = o.precision;
+  p->tier = o.precision == HFX_PREC_TIERED ? 1 : o.precision == HFX_PREC_FP32 ? 2 : 0;
+  p->tau = (float)o.tier_tau;
   p->scheduler = o.scheduler;
   p->stream = (hipStream_t)o.stream;
   p->max_bytes = o.max_device_bytes;
@@ -608,7 +618,8 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   p->wave_doubles = (16 * (int64_t)main_maxn() * main_maxn() + 64 + 31) / 32 * 32;
   p->wg_off = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
   const int64_t wg_doubles = (int64_t)p->rows_cap * 64 + (int64_t)max_p * max_n * 64 + 64;
-  const int64_t slot = p->wg_off + wg_doubles;
+  p->ub_off = p->wg_off + wg_doubles;
+  const int64_t slot = p->ub_off + (p->tier == 1 ? nfg : 0);  // two float bounds per (F,G)
   (void)min_n;
   p->ld3 = max_n;
   const size_t lds = main_static_lds() + main_dyn_lds(p->rows_cap, p->cols_cap, p->ld3);
@@ -632,6 +643,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
           *d_ccol = nullptr, *d_cR = nullptr, *d_crow = nullptr, *d_vrow = nullptr, *d_vcol = nullptr,
           *d_qsrc = nullptr;
   long long *d_coff = nullptr, *d_voff = nullptr, *d_doff = nullptr;
+  float *d_C32 = nullptr, *d_CT32 = nullptr;
   double *d_C = nullptr, *d_CT = nullptr, *d_V = nullptr, *d_gV = nullptr, *d_gD = nullptr, *d_D = nullptr,
          *d_S = nullptr, *d_scr = nullptr;
   CNorm *d_cn = nullptr;
@@ -650,6 +662,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       (st = p->upload(&d_cstart, c_start)) || (st = p->upload(&d_ccol, c_col)) || (st = p->upload(&d_crow, c_row)) ||
       (st = p->upload(&d_cR, c_Rp)) || (st = p->upload(&d_coff, c_off)) || (st = p->upload(&d_C, cstage)) ||
       (st = p->dalloc(&d_CT, cstage.size())) ||
+      (p->tier && ((st = p->dalloc(&d_C32, cstage.size())) || (st = p->dalloc(&d_CT32, cstage.size())))) ||
       (st = p->upload(&d_vrow, v_row)) || (st = p->upload(&d_vcol, v_col)) || (st = p->upload(&d_voff, v_off)) ||
       (st = p->upload(&d_V, vstage)) || (st = p->upload(&d_qsrc, qsrc)) || (st = p->dalloc(&d_cn, nC)) ||
       (st = p->dalloc(&d_gV, nV)) || (st = p->upload(&d_ptoff, ptab_off)) || (st = p->upload(&d_pstart, pstart)) ||
@@ -688,6 +701,8 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   P.local_of = d_localof;
   P.Cbuf = d_C;
   P.CTbuf = d_CT;
+  P.C32 = d_C32;
+  P.CT32 = d_CT32;
   P.c_off = d_coff;
   P.c_col = d_ccol;
   P.c_R = d_cR;
@@ -733,6 +748,8 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
                           p->d_row_dev, p->d_col_dev, p->dbase_dev};
     for (const void *q : must)
       if (!q) return fail(HFX_ERR_OOM, "internal: a device buffer of the plan was not allocated");
+    if (p->tier && (!P.C32 || !P.CT32))
+      return fail(HFX_ERR_OOM, "internal: the FP32 operand copies were not allocated");
   }
   p->lpt_order = p->order;
   if (p->scheduler == HFX_SCHED_MLP) {
@@ -763,6 +780,10 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   // ---- plan-time kernels: C norms, CS-ERI factors, V norms
   HIPCHK(p, launch_cnorm(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_cn, p->stream));
   HIPCHK(p, launch_ctrans(d_C, d_coff, d_crow, d_ccol, d_nao, d_nabf, nC, d_CT, p->stream));
+  if (p->tier) {
+    HIPCHK(p, launch_to_f32(d_C, d_C32, (long long)cdoubles, p->stream));
+    HIPCHK(p, launch_to_f32(d_CT, d_CT32, (long long)cdoubles, p->stream));
+  }
   HIPCHK(p, launch_cq(d_C, d_coff, d_crow, d_ccol, d_V, d_voff, d_qsrc, d_nao, d_nabf, nC, d_cn, p->stream));
   HIPCHK(p, launch_vnorm(d_V, d_voff, d_vrow, d_vcol, d_nabf, nV, d_gV, p->stream));
   HIPCHK(p, hipEventCreate(&p->ev0));
@@ -858,7 +879,7 @@ static hfx_status enqueue_core(hfx_plan *p, double *const *sigma, bool eager) {
   HIPCHK(p, launch_reset(P.ticket, P.counters, P.flops, p->stream));
   if (eager) HIPCHK(p, hipEventRecord(p->ev1, p->stream));
   if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles,
-                                          p->wg_off, p->stream, eager));
+                                          p->wg_off, p->ub_off, p->tier, p->tau, p->stream, eager));
   if (eager) HIPCHK(p, hipEventRecord(p->ev2, p->stream));
   for (int c = 0; c < p->n_cells; ++c) {
     const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
@@ -954,10 +975,18 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     HIPCHK(p, hipMemcpy(fl, P.flops, sizeof(fl), hipMemcpyDeviceToHost));
     stats->flops_paper = fl[0];
     stats->flops_contract = fl[1];
-    stats->flops_tier[0] = fl[1];
+    // matrix-core FLOPs issued (16x16x4 in either precision: 2048 each); the FP32 share of the
+    // contraction FLOPs is estimated by the FP32 share of the block-product instructions
+    const double mR = (double)cnt[kCntMfmaR], mL = (double)cnt[kCntMfmaL];
+    const double mR32 = (double)cnt[kCntMfmaR32], mL32 = (double)cnt[kCntMfmaL32];
+    const double gemm = mR + mL + mR32 + mL32;
+    const double share32 = gemm > 0 ? (mR32 + mL32) / ((double)cnt[kCntMfmaY] + gemm) : 0.0;
+    stats->flops_tier[1] = fl[1] * share32;
+    stats->flops_tier[0] = fl[1] - stats->flops_tier[1];
     stats->mfma_flops[0] = 2048.0 * (double)cnt[kCntMfmaY];
-    stats->mfma_flops[1] = 2048.0 * (double)cnt[kCntMfmaR];
-    stats->mfma_flops[2] = 2048.0 * (double)cnt[kCntMfmaL];
+    stats->mfma_flops[1] = 2048.0 * (mR + mR32);
+    stats->mfma_flops[2] = 2048.0 * (mL + mL32);
+    stats->mfma_flops_fp32 = 2048.0 * (mR32 + mL32);
     float ms0 = 0, ms1 = 0;
     HIPCHK(p, hipEventElapsedTime(&ms0, p->ev0, p->ev2));
     HIPCHK(p, hipEventElapsedTime(&ms1, p->ev1, p->ev2));

@@ -112,16 +112,16 @@ def test_cfg1_full():
     assert e[0] < 0
 
 
-def _supercell_vs_primitive(name, eps, rel):
+def _supercell_vs_primitive(name, eps, rel, **opt):
     torch = _torch()
-    log(f"case {name} eps={eps}: GPU full supercell vs oracle primitive cell")
+    log(f"case {name} eps={eps} {opt}: GPU full supercell vs oracle primitive cell")
     wp = hs.make_workload(name + "prim", eps=eps)
     t = time.time()
     ref = oracle.run(wp.cells[0], wp.C[0], wp.V[0], wp.D[0], wp.thresholds, n_threads=16)
     log(f"{name} oracle (2 home atoms) {time.time() - t:.1f}s")
     ws = hs.make_workload(name, eps=eps)
     t = time.time()
-    sig, e, st = gpu_build(ws)
+    sig, e, st = gpu_build(ws, **opt)
     log(f"{name} gpu plan+build {time.time() - t:.1f}s stats {st}")
     cs, cp = ws.cells[0], wp.cells[0]
     pi, pR = hs.map_to_primitive(cs, cp)
