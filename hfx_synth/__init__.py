@@ -408,22 +408,23 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
     cfg1      2-atom primitive cell, 13/40, all blocks within 12 bohr, no screening
     cfg2      64 atoms (2^3 conventional cells), 13/40, C within 16 bohr, eps 1e-6
     cfg3      512 atoms (4^3 conventional cells), 13/60, C within 16 bohr, eps 1e-6 (or 1e-4)
+    cfg2prim  the 2-atom primitive cell of cfg2 with identical keyed blocks
     cfg3prim  the 2-atom primitive cell of cfg3 with identical keyed blocks
     cfg4      48 cells of 1..3 x 1..3 x 1..3 conventional cells, species 13/60 and 27/100
               drawn per site with p = 1/2, C within 12 bohr, V within 24, D within 30, eps 1e-4
     cfg5      4096 atoms (8^3 conventional cells), 13/60, eps 1e-6
     tiny      user-sized cells for tests (keywords: kind, n, species_table, r_c, r_v, r_d, eps)
     """
-    idx = {"cfg1": 0, "cfg2": 1, "cfg3": 2, "cfg3prim": 2, "cfg4": 3, "cfg5": 4, "tiny": 9}[name]
+    idx = {"cfg1": 0, "cfg2": 1, "cfg2prim": 1, "cfg3": 2, "cfg3prim": 2, "cfg4": 3, "cfg5": 4, "tiny": 9}[name]
     seed = SEED0 + idx if seed is None else seed
     if name == "cfg1":
         p = Params(r_c=12.0, r_v=12.0, r_d=12.0)
         cells = [make_cell("primitive", species_table=((13, 40),))]
         th = 0.0 if eps is None else eps
-    elif name in ("cfg2", "cfg3", "cfg3prim", "cfg5"):
+    elif name in ("cfg2", "cfg2prim", "cfg3", "cfg3prim", "cfg5"):
         p = Params(r_c=16.0, r_v=36.0, r_d=45.0)
-        nabf = 40 if name == "cfg2" else 60
-        if name == "cfg3prim":
+        nabf = 40 if name.startswith("cfg2") else 60
+        if name.endswith("prim"):
             cells = [make_cell("primitive", species_table=((13, nabf),))]
         else:
             n = {"cfg2": 2, "cfg3": 4, "cfg5": 8}[name]

@@ -125,3 +125,48 @@ def test_rejects_unknown_scheduler_and_null_out():
     assert L.hfx_plan_create(1, ctypes.byref(c), ctypes.byref(C), ctypes.byref(V), ctypes.byref(D),
                              ctypes.byref(th), None, None) == A.HFX_ERR_ARG
     assert L.hfx_build(None, None, None, None) == A.HFX_ERR_ARG
+
+
+def test_rejects_unavailable_or_invalid_precision():
+    w = _tiny()
+    keep, c, C, V, D, th = _cstructs(w)
+    opt = A.Options()
+    opt.precision = A.PREC_BF16X3
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_UNSUPPORTED and "BF16" in msg
+    opt = A.Options()
+    opt.precision = 7
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_ARG
+    opt = A.Options()
+    opt.precision = A.PREC_TIERED
+    opt.tier_tau = -1.0
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_ARG and "tier_tau" in msg
+
+
+def test_mlp_entry_points_validate_before_launch():
+    L = A.lib()
+    assert L.hfx_mlp_n_params(8, 32) == 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
+    P = ctypes.c_void_p(1)  # never dereferenced: the sizes are rejected first
+    assert L.hfx_mlp_predict(0, 32, P, P, 1, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_predict(8, 65, P, P, 1, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_loss_grad(8, 32, None, P, P, 1, P, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_train(8, 32, P, P, P, 1, 10, ctypes.c_float(0.0), None, None) == A.HFX_ERR_ARG
+    assert L.hfx_item_features(None, None, None, None) == A.HFX_ERR_ARG
+
+
+def test_scheduler_model_file_roundtrip_and_list_schedule(tmp_path):
+    from paper_2009_12505_amd import sched
+    m = sched.CostModel(4, np.arange(8, dtype=np.float32), np.ones(8, np.float32),
+                        np.linspace(-1, 1, sched.n_params(4)).astype(np.float32), np.zeros(0))
+    sched.save(m, tmp_path / "m.bin")
+    m2 = sched.load(tmp_path / "m.bin")
+    assert m2.hidden == 4 and np.array_equal(m2.params, m.params) and np.array_equal(m2.mu, m.mu)
+    # greedy list scheduling: longest first on 2 machines is optimal here, plan order is not
+    costs = np.array([1.0, 1.0, 2.0])
+    assert sched.list_schedule_makespan(costs, [2, 0, 1], 2) == 2.0
+    assert sched.list_schedule_makespan(costs, [0, 1, 2], 2) == 3.0
+    with pytest.raises(ValueError):
+        (tmp_path / "bad.bin").write_bytes(b"NOTAMODEL" + bytes(64))
+        sched.load(tmp_path / "bad.bin")

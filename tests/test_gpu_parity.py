@@ -162,6 +162,19 @@ def test_cfg3_eps1e4_full_vs_primitive():
     _supercell_vs_primitive("cfg3", 1e-4, 1e-11)
 
 
+@pytest.mark.timeout(900)
+def test_cfg3_eps1e6_full_vs_primitive():
+    """The benchmark workload itself (512 atoms, eps 1e-6, FP64, the launch configuration bench.py
+    times): every Sigma block against the oracle's primitive-cell block of the same atom pair."""
+    _supercell_vs_primitive("cfg3", 1e-6, 1e-11)
+
+
+@pytest.mark.timeout(900)
+def test_cfg2_full_vs_primitive():
+    """64-atom supercell (2^3 conventional cells), 13 AO / 40 ABF, C within 16 bohr, eps 1e-6."""
+    _supercell_vs_primitive("cfg2", 1e-6, 1e-11)
+
+
 def _combine(ws):
     """One batched workload from several single-cell workloads."""
     import dataclasses
