@@ -100,13 +100,15 @@ typedef struct {             /* Sec. III B and III C; 0 keeps every non-zero bou
   double eps_cs_mat;         /* keep a unit iff each of the three bounds > eps_cs_mat        */
 } hfx_thresholds;
 
-/* precision of the block contractions; screening bounds, accumulation into
- * Sigma and the energy are FP64 in every mode */
-#define HFX_PREC_FP64 0     /* every contraction in FP64                                   */
-#define HFX_PREC_FP32 1     /* every contraction on FP32 MFMA, FP64 accumulation           */
-#define HFX_PREC_TIERED 2   /* per unit: FP64 if its bound > tier_tau, else FP32 MFMA      */
-#define HFX_PREC_BF16X3 3   /* split-BF16x3 MFMA for units with bound <= tier_tau_bf, FP32 /
-                               FP64 tiers above it                                          */
+/* precision of the block products that contract C with the (VC)D intermediates
+ * (terms 1-4); the screening bounds, Y = V C, T3, T4, the Gram matrices, the
+ * accumulation into Sigma and the energy are FP64 in every mode */
+#define HFX_PREC_FP64 0     /* every block product in FP64                                 */
+#define HFX_PREC_FP32 1     /* every block product on FP32 MFMA (FP32 operands and sums)   */
+#define HFX_PREC_TIERED 2   /* a block product runs on FP32 MFMA when the stage-2 bound of
+                               every kept unit in it is <= tier_tau, else in FP64           */
+#define HFX_PREC_BF16X3 3   /* split-BF16x3: not available, hfx_plan_create returns
+                               HFX_ERR_UNSUPPORTED                                          */
 
 #define HFX_SCREEN_PRE 1u    /* block max-abs pre-screening of C, V, D                     */
 #define HFX_SCREEN_CS_ERI 2u /* CS-ERI quartet test                                        */
@@ -116,14 +118,15 @@ typedef struct {             /* Sec. III B and III C; 0 keeps every non-zero bou
 #define HFX_SCREEN_ALL 31u
 
 #define HFX_SCHED_PLAN 0    /* work items in plan order                                    */
-#define HFX_SCHED_LPT 1     /* longest-processing-time first on the screened unit counts   */
+#define HFX_SCHED_LPT 1     /* longest-processing-time first on |N_C(A)| |N_C(B)|           */
 #define HFX_SCHED_MLP 2     /* order by the learned cost model (mlp_weights)               */
 
 typedef struct {
   int32_t precision;          /* HFX_PREC_*                                                 */
   uint32_t stages;            /* HFX_SCREEN_* bitmask; 0 means HFX_SCREEN_ALL               */
-  double tier_tau;            /* TIERED / BF16X3: units with bound <= tier_tau leave FP64   */
-  double tier_tau_bf;         /* BF16X3: units with bound <= tier_tau_bf use split-BF16x3   */
+  double tier_tau;            /* TIERED: a block product whose kept units all have a stage-2
+                                 bound <= tier_tau runs on FP32 MFMA (finite, >= 0)         */
+  double tier_tau_bf;         /* reserved for split-BF16x3 (not available); ignored         */
   int32_t scheduler;          /* HFX_SCHED_*                                                */
   const char *mlp_weights;    /* file written by the scheduler trainer, or NULL             */
   void *stream;               /* hipStream_t for plan-time and build work; NULL = default   */
@@ -149,11 +152,14 @@ typedef struct {               /* filled by hfx_build when non-NULL (synchronise
                                   the kept units (padding and screened-out work excluded)   */
   double flops_paper;          /* FLOPs of the same kept units counted as in Algorithm 3:
                                   T and Htilde per unit, Y, T3, T4 once per (A,B,G)          */
-  double flops_tier[3];        /* flops_contract split by precision: FP64 / FP32 / BF16x3   */
+  double flops_tier[3];        /* flops_contract split by precision: FP64 / FP32 / BF16x3; the
+                                  FP32 part is flops_contract times the FP32 share of the
+                                  matrix-core instructions issued                           */
   double mfma_flops[3];        /* matrix-core FLOPs issued (with padding): G side and masks,
                                   terms 3+4, terms 1+2                                       */
   double ms_total;             /* device time of the build (events on the plan stream)      */
-  double ms_main;              /* device time of the main persistent kernel                 */
+  double ms_main;              /* device time of the main persistent kernel (graph mode: the
+                                  whole graph, as ms_total)                                  */
   double phase_share[6];       /* share of the summed per-item time spent in: screening,
                                   Y = VC and the G-side products, stage-2/3 masks, terms 3+4,
                                   terms 1+2, item set-up                                     */
@@ -214,7 +220,10 @@ hfx_status hfx_item_profile(hfx_plan *plan, int64_t *n_items, int64_t *cycles, i
  * with n_in inputs and n_hidden units per hidden layer; FP32 parameters laid
  * out as W1[n_hidden][n_in], b1, W2[n_hidden][n_hidden], b2, w3, b3.
  * All arrays are device memory; stream as in hfx_options.  The model never
- * changes which units are computed, only the order in which items run.    */
+ * changes which units are computed, only the order in which items run.
+ * Errors: HFX_ERR_ARG for n_in outside 1..16, n_hidden outside 1..64, NULL
+ * arrays, n < 0, epochs < 0 or lr <= 0; HFX_ERR_OOM if the optimizer state
+ * cannot be allocated; HFX_ERR_HIP if a launch fails.                      */
 int64_t hfx_mlp_n_params(int32_t n_in, int32_t n_hidden);
 
 /* y[i] = model(X[i*n_in ..]) for n samples. */

@@ -528,7 +528,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   p->n_items = (int64_t)p->items.size();
   p->order.resize(p->n_items);
   std::iota(p->order.begin(), p->order.end(), 0);
-  if (p->scheduler == HFX_SCHED_LPT)
+  if (p->scheduler != HFX_SCHED_PLAN)  // the learned order starts from LPT until a build has run
     std::stable_sort(p->order.begin(), p->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
 
   // ---- D pattern: compact offsets, sorted lookup, pair tables
