@@ -946,9 +946,13 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     std::vector<float> pred(p->n_items);
     HIPCHK(p, hipMemcpyAsync(pred.data(), p->mlp_y, pred.size() * sizeof(float), hipMemcpyDeviceToHost, p->stream));
     HIPCHK(p, hipStreamSynchronize(p->stream));
-    std::vector<int32_t> ord(p->n_items);
+    // longest predicted first, on a grid of 0.1 (predictions are standardised log times) so that
+    // items of similar cost keep the plan order, which groups the items of one atom A and lets
+    // concurrent workgroups share its C blocks in cache
+    std::vector<int32_t> ord(p->n_items), bucket(p->n_items);
+    for (int64_t i = 0; i < p->n_items; ++i) bucket[i] = (int32_t)std::floor(pred[i] * 10.0f);
     std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return pred[x] > pred[y]; });
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bucket[x] > bucket[y]; });
     HIPCHK(p, hipMemcpyAsync(const_cast<int32_t *>(P.order), ord.data(), ord.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, p->stream));
     HIPCHK(p, hipStreamSynchronize(p->stream));
