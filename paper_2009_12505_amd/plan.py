@@ -77,6 +77,8 @@ class Plan:
         th = A.Thresholds(thresholds["eps_C"], thresholds["eps_V"], thresholds["eps_D"], thresholds["eps_cs_eri"],
                           thresholds["eps_cs_mat"])
         hs = None if home_subset is None else _arr(home_subset, np.int32)
+        if hs is not None and hs.shape[0] == 0:
+            hs = np.zeros(1, np.int32)[:0]  # an empty subset still passes a non-NULL pointer
         if stream is None:
             stream = torch.cuda.current_stream()
         self._stream = stream

@@ -170,3 +170,10 @@ def test_scheduler_model_file_roundtrip_and_list_schedule(tmp_path):
     with pytest.raises(ValueError):
         (tmp_path / "bad.bin").write_bytes(b"NOTAMODEL" + bytes(64))
         sched.load(tmp_path / "bad.bin")
+
+
+def test_rejects_blocks_beyond_the_kernel_limits():
+    w = hs.make_workload("tiny", kind="primitive", species_table=((33, 5),), r_c=5.0, r_v=5.0, r_d=5.0)
+    keep, c, C, V, D, th = _cstructs(w)
+    st, msg = _create(c, C, V, D, th)
+    assert st == A.HFX_ERR_UNSUPPORTED and "n_ao" in msg
