@@ -1,6 +1,6 @@
 """Benchmark: one HFX build (Sigma^X of a 512-atom Si-like supercell) per step.
 
-    python bench.py [--steps K] [--warmup W] [--eps 1e-6] [--precision fp64]
+    python bench.py [--steps K] [--warmup W] [--eps 1e-6] [--precision fp64|tiered|fp32 [--tau T]] [--graph]
 
 Workload: 4x4x4 conventional diamond cells (512 atoms, a = 10.26 bohr), 13 AOs / 60 ABFs
 per atom, C within 16 bohr, screened V (omega = 0.11/bohr), all five thresholds = eps.
@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "tiered", "fp32"])
     ap.add_argument("--tau", type=float, default=1e-3, help="tier bound of the tiered form")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the build as one captured HIP graph (kernel time = whole graph)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -112,7 +114,7 @@ def main():
     t0 = time.perf_counter()
     from paper_2009_12505_amd import PREC_FP32, PREC_FP64, PREC_TIERED
     prec = {"fp64": PREC_FP64, "tiered": PREC_TIERED, "fp32": PREC_FP32}[args.precision]
-    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau)
+    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau, use_graph=args.graph)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     progress(f"plan created in {t_plan:.1f}s")
@@ -159,7 +161,7 @@ def main():
                                f"atom, C within 16 bohr, HSE-screened V, all thresholds {args.eps:g}, "
                                f"precision {args.precision}",
                    "eps": args.eps, "n_atoms": n_atoms, "precision": args.precision,
-                   "tier_tau": args.tau if args.precision == "tiered" else None},
+                   "tier_tau": args.tau if args.precision == "tiered" else None, "hip_graph": args.graph},
         "flops_fp32_share": round(f32 / fl_alg, 4) if fl_alg > 0 else 0.0,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": round(peak, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
