@@ -88,8 +88,8 @@ def main():
                     help="only run a plain device copy of known size (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the build runs on a single MI355X; multi-GPU sharding is "
-              "described in DESIGN.md but not part of this benchmark", file=sys.stderr)
+        print("bench.py measures one GPU: the build runs on a single MI355X; sharding the work items "
+              "over several GPUs is not part of this benchmark", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -199,7 +199,7 @@ hfx_status hfx_sigma_layout(const hfx_plan *plan, int32_t cell, hfx_blocks *layo
  *   stats  optional; when non-NULL the call synchronises and fills it
  * Stream-ordered on opt.stream; returns before completion unless stats is
  * requested.  D is read during the call's stream work; keep it alive until
- * the stream has passed this build. */
+ * the stream has passed this call's work. */
 hfx_status hfx_build(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, hfx_build_stats *stats);
 
 /* E_x = 1/2 <D, Sigma^X> per cell with compensated FP64 summation over the

@@ -379,7 +379,7 @@ static int do_build(ref_ctx *x, const int32_t *home, int32_t n_home, double *sig
   } else {
     memset(is_home, 1, (size_t)x->n_atoms);
   }
-  /* work items: kept V blocks whose row atom A is a home atom of this build */
+  /* work items: kept V blocks whose row atom A is one of the selected home atoms */
   int64_t n_items = 0;
   int64_t *items = (int64_t *)malloc(sizeof(int64_t) * (size_t)(x->V.n + 1));
   for (int64_t k = 0; k < x->V.n; ++k)

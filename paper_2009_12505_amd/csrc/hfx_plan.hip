@@ -282,7 +282,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   hfx_options o{};
   if (opt) o = *opt;
   if (o.precision == HFX_PREC_BF16X3)
-    return fail(HFX_ERR_UNSUPPORTED, "split-BF16x3 block products are not available in this build");
+    return fail(HFX_ERR_UNSUPPORTED, "split-BF16x3 block products are not implemented");
   if (o.precision < HFX_PREC_FP64 || o.precision > HFX_PREC_TIERED)
     return fail(HFX_ERR_ARG, "unknown precision %d", o.precision);
   if (o.precision == HFX_PREC_TIERED && !(o.tier_tau >= 0 && std::isfinite(o.tier_tau)))
