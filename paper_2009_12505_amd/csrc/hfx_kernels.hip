@@ -208,10 +208,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// a 16x16 tile product over K <= 32 with every operand load issued before the first MFMA (the
+// G-side products are short, so one wait per tile instead of one per K step); fa(row, k) and
+// fb(k, col) return 0 outside the operands
+template <class FA, class FB>
+__device__ __forceinline__ d4 tile_mm_burst(int K, FA fa, FB fb, d4 acc) {
+  const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
+  double a[8], b[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int k = 4 * s + kk;
+    a[s] = k < K ? fa(l16, k) : 0.0;
+    b[s] = k < K ? fb(k, l16) : 0.0;
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    if (4 * s < K) acc = mfma64(a[s], b[s], acc);
+  return acc;
+}
+
 // ---------------------------------------------------------------------------------------------
 // G side for one alive G, by one wave: Y = V_AB C_BG, T4 = D_AB Y, T3 = Y D_AG^T (per alpha),
-// the Gram matrices N1[b] = Y_b^T Y_b and M2[g] = Y_g^T Y_g, and the slice norms of stages 2, 3
-__device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, const double *Vsrc) {
+// the Gram matrices N1[b] = Y_b^T Y_b and M2[g] = Y_g^T Y_g, and the slice norms of stages 2, 3.
+// Kept out of line: its load bursts need many registers, and inlined they would push the
+// register allocation of the block products past the budget of two waves per SIMD.
+__device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, const double *Vsrc) {
   const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
   const int j = L.a_j[jj];
   const int PA = L.PA, PB = L.PB, na = L.na, nb = L.nb, ng = L.g_n[j];
@@ -219,7 +240,8 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
   const double *C = P.Cbuf + L.g_coff[j];
   double *Y = slot + L.a_y[jj];
   unsigned long long nm = 0;
-  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]; four alpha tiles share each C fragment
+  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]; four alpha tiles share each C fragment,
+  // which is fetched 32 K at a time before its MFMAs
   const int mt = (PA + 15) >> 4, nt = (N + 15) >> 4;
   for (int rg = 0; rg < mt; rg += 4) {
     for (int ct = 0; ct < nt; ++ct) {
@@ -228,21 +250,25 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
       d4 acc[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
-      int row[4];
+      for (int k0 = 0; k0 < PB; k0 += 32) {
+        double bv[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) row[u] = ((rg + u) << 4) + l16;
-      double b_c = (cok && kk < PB) ? C[(long long)kk * N + col] : 0.0;
-      for (int k0 = 0; k0 < PB; k0 += 4) {
-        const int k = k0 + kk;
-        const int kn = k + 4;
-        const double b_n = (k0 + 4 < PB && cok && kn < PB) ? C[(long long)kn * N + col] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (rg + u >= mt) break;
-          const double a = (row[u] < PA && k < PB) ? Vsrc[row[u] * PB + k] : 0.0;
-          acc[u] = mfma64(a, b_c, acc[u]);
+        for (int s = 0; s < 8; ++s) {
+          const int k = k0 + 4 * s + kk;
+          bv[s] = (cok && k < PB) ? C[(long long)k * N + col] : 0.0;
         }
-        b_c = b_n;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          if (k0 + 4 * s >= PB) break;
+          const int k = k0 + 4 * s + kk;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (rg + u >= mt) break;
+            const int row = ((rg + u) << 4) + l16;
+            const double a = (row < PA && k < PB) ? Vsrc[row * PB + k] : 0.0;
+            acc[u] = mfma64(a, bv[s], acc[u]);
+          }
+        }
       }
       nm += (unsigned long long)min(4, mt - rg) * ((PB + 3) >> 2);
 #pragma unroll
@@ -255,23 +281,43 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
     }
   }
   __threadfence_block();
-  // T4[(al,a)][g] = sum_b D_AB[a][b] Y[al][b][g]
+  // T4[(al,a)][g] = sum_b D_AB[a][b] Y[al][b][g]: D_AB fragments once, two alphas' Y at a time
   double t4max = 0.0;
   if (L.okAB) {
     double *T4 = slot + L.a_t4[jj];
     for (int g0 = 0; g0 < ng; g0 += 16) {
       double sq = 0.0;  // sum over (al, a) of T4^2 for column g = g0 + l16 (this lane's rows)
+      const int g = g0 + l16;
       for (int a0 = 0; a0 < na; a0 += 16) {
-        for (int al = 0; al < PA; ++al) {
-          const double *Ya = Y + (long long)al * N;
-          const d4 h = tile_mm(
-              nb, [&](int r, int k) { return (a0 + r < na && k < nb) ? L.DAB[(a0 + r) * nb + k] : 0.0; },
-              [&](int k, int c) { return (k < nb && g0 + c < ng) ? Ya[k * ng + g0 + c] : 0.0; });
-          for (int e = 0; e < 4; ++e) {
-            const int a = a0 + kk + 4 * e, g = g0 + l16;
-            if (a < na && g < ng) {
-              T4[((long long)al * na + a) * ng + g] = h[e];
-              sq += h[e] * h[e];
+        double av[MAXN / 4];
+#pragma unroll
+        for (int s = 0; s < MAXN / 4; ++s) {
+          const int k = 4 * s + kk;
+          av[s] = (a0 + l16 < na && k < nb) ? L.DAB[(a0 + l16) * nb + k] : 0.0;
+        }
+        for (int al0 = 0; al0 < PA; al0 += 2) {
+          double bv[2][MAXN / 4];
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int s = 0; s < MAXN / 4; ++s) {
+              const int k = 4 * s + kk, al = al0 + q;
+              bv[q][s] = (al < PA && k < nb && g < ng) ? Y[(long long)al * N + k * ng + g] : 0.0;
+            }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int al = al0 + q;
+            if (al >= PA) break;
+            d4 h = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < MAXN / 4; ++s)
+              if (4 * s < nb) h = mfma64(av[s], bv[q][s], h);
+            for (int e = 0; e < 4; ++e) {
+              const int a = a0 + kk + 4 * e;
+              if (a < na && g < ng) {
+                T4[((long long)al * na + a) * ng + g] = h[e];
+                sq += h[e] * h[e];
+              }
             }
           }
         }
@@ -282,7 +328,7 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
       t4max = fmax(t4max, wave_max(sq));
     }
   }
-  // T3[(al,a)][b] = sum_g D_AG[a][g] Y[al][b][g]
+  // T3[(al,a)][b] = sum_g D_AG[a][g] Y[al][b][g]: D_AG fragments once, two alphas' Y at a time
   double t3max = 0.0;
   const int dAG = L.g_dAG[j];
   if (dAG >= 0 && P.keepD[dAG]) {
@@ -290,17 +336,37 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
     double *T3 = slot + L.a_t3[jj];
     for (int b0 = 0; b0 < nb; b0 += 16) {
       double sq = 0.0;  // sum over (al, a) of T3^2 for column b = b0 + l16 (this lane's rows)
+      const int b = b0 + l16;
       for (int a0 = 0; a0 < na; a0 += 16) {
-        for (int al = 0; al < PA; ++al) {
-          const double *Ya = Y + (long long)al * N;
-          const d4 h = tile_mm(
-              ng, [&](int r, int k) { return (a0 + r < na && k < ng) ? DAG[(a0 + r) * ng + k] : 0.0; },
-              [&](int k, int c) { return (k < ng && b0 + c < nb) ? Ya[(b0 + c) * ng + k] : 0.0; });
-          for (int e = 0; e < 4; ++e) {
-            const int a = a0 + kk + 4 * e, b = b0 + l16;
-            if (a < na && b < nb) {
-              T3[((long long)al * na + a) * nb + b] = h[e];
-              sq += h[e] * h[e];
+        double av[MAXN / 4];
+#pragma unroll
+        for (int s = 0; s < MAXN / 4; ++s) {
+          const int k = 4 * s + kk;
+          av[s] = (a0 + l16 < na && k < ng) ? DAG[(a0 + l16) * ng + k] : 0.0;
+        }
+        for (int al0 = 0; al0 < PA; al0 += 2) {
+          double bv[2][MAXN / 4];
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int s = 0; s < MAXN / 4; ++s) {
+              const int k = 4 * s + kk, al = al0 + q;
+              bv[q][s] = (al < PA && k < ng && b < nb) ? Y[(long long)al * N + b * ng + k] : 0.0;
+            }
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int al = al0 + q;
+            if (al >= PA) break;
+            d4 h = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < MAXN / 4; ++s)
+              if (4 * s < ng) h = mfma64(av[s], bv[q][s], h);
+            for (int e = 0; e < 4; ++e) {
+              const int a = a0 + kk + 4 * e;
+              if (a < na && b < nb) {
+                T3[((long long)al * na + a) * nb + b] = h[e];
+                sq += h[e] * h[e];
+              }
             }
           }
         }
@@ -318,9 +384,14 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
     double tr = 0.0;
     for (int g0 = 0; g0 < ng; g0 += 16)
       for (int h0 = 0; h0 < ng; h0 += 16) {
-        const d4 h = tile_mm(
-            PA, [&](int r, int k) { return (g0 + r < ng && k < PA) ? Y[(long long)k * N + b * ng + g0 + r] : 0.0; },
-            [&](int k, int c) { return (k < PA && h0 + c < ng) ? Y[(long long)k * N + b * ng + h0 + c] : 0.0; });
+        d4 h = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < PA; k0 += 32) {
+          const double *Yk = Y + (long long)k0 * N + b * ng;
+          const int K = min(32, PA - k0);
+          h = tile_mm_burst(
+              K, [&](int r, int k) { return g0 + r < ng ? Yk[(long long)k * N + g0 + r] : 0.0; },
+              [&](int k, int c) { return h0 + c < ng ? Yk[(long long)k * N + h0 + c] : 0.0; }, h);
+        }
         for (int e = 0; e < 4; ++e) {
           const int g = g0 + kk + 4 * e, g2 = h0 + l16;
           if (g < ng && g2 < ng) {
@@ -338,9 +409,14 @@ __device__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, c
     double tr = 0.0;
     for (int b0 = 0; b0 < nb; b0 += 16)
       for (int c0 = 0; c0 < nb; c0 += 16) {
-        const d4 h = tile_mm(
-            PA, [&](int r, int k) { return (b0 + r < nb && k < PA) ? Y[(long long)k * N + (b0 + r) * ng + g] : 0.0; },
-            [&](int k, int c) { return (k < PA && c0 + c < nb) ? Y[(long long)k * N + (c0 + c) * ng + g] : 0.0; });
+        d4 h = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < PA; k0 += 32) {
+          const double *Yk = Y + (long long)k0 * N + g;
+          const int K = min(32, PA - k0);
+          h = tile_mm_burst(
+              K, [&](int r, int k) { return b0 + r < nb ? Yk[(long long)k * N + (b0 + r) * ng] : 0.0; },
+              [&](int k, int c) { return c0 + c < nb ? Yk[(long long)k * N + (c0 + c) * ng] : 0.0; }, h);
+        }
         for (int e = 0; e < 4; ++e) {
           const int b = b0 + kk + 4 * e, b2 = c0 + l16;
           if (b < nb && b2 < nb) {
