@@ -895,6 +895,89 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 }
 
 // ---------------------------------------------------------------------------------------------
+// One work item of the Y contraction of a GEMM-L column block [c0, c1), by one wave:
+//   wi < NW (term 1, alpha part wi):  H1[a][b] += sum_{al in part, c} P[(al,a)][c] Y_G(c)[al][b][g(c)]
+//   wi >= NW (term 2, G = jj0 + wi - NW):  Sigma(A,G)[a][g] -= sum_{al, c} P[(al,a)][c] Y_G[al][b(c)][g]
+// The operands of up to eight K steps are loaded before their MFMAs; kept out of line so that
+// its registers do not count against the block products.  Returns the MFMAs issued.
+__device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const short *col2jj, const double *Pb,
+                                                          const double *slot, double *Sbuf, int wi, int c0, int c1,
+                                                          int jj0, unsigned long long t2m, bool t1any) {
+  const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
+  const int PA = L.PA, na = L.na, nb = L.nb;
+  unsigned long long nm = 0;
+  if (t1any && wi < NW) {
+    const int al0 = wi * PA / NW, al1 = (wi + 1) * PA / NW, nc = c1 - c0;
+    for (int a0 = 0; a0 < na; a0 += 16)
+      for (int b0 = 0; b0 < nb; b0 += 16) {
+        d4 h = {0, 0, 0, 0};
+        for (int al = al0; al < al1; ++al)
+          for (int cg = 0; cg < nc; cg += 32) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+              const int cl = cg + 4 * s + kk;
+              double x = 0.0, y = 0.0;
+              if (cl < nc) {
+                const int c = c0 + cl, jj = col2jj[c], j = L.a_j[jj];
+                const int cc = c - L.a_col0[jj], ng = L.g_n[j];
+                if (cc < ng) {
+                  if (a0 + l16 < na) x = Pb[(long long)(al * na + a0 + l16) * BN + cl];
+                  if (b0 + l16 < nb) y = slot[L.a_y[jj] + ((long long)al * nb + b0 + l16) * ng + cc];
+                }
+              }
+              av[s] = x;
+              bv[s] = y;
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+              if (cg + 4 * s < nc) {
+                h = mfma64(av[s], bv[s], h);
+                ++nm;
+              }
+          }
+        for (int e = 0; e < 4; ++e) {
+          const int a = a0 + kk + 4 * e, b = b0 + l16;
+          if (a < na && b < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + b], h[e]);
+        }
+      }
+    return nm;
+  }
+  const int q = wi - (t1any ? NW : 0);
+  if (!((t2m >> q) & 1ull)) return 0;
+  const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
+  const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
+  const int bc0 = max(c0, gb), bc1 = min(c1, g1);
+  const double *Yj = slot + L.a_y[jj];
+  double *S = Sbuf + L.g_dAGoff[j];
+  for (int a0 = 0; a0 < na; a0 += 16)
+    for (int g0 = 0; g0 < ng; g0 += 16) {
+      d4 h = {0, 0, 0, 0};
+      for (int al = 0; al < PA; ++al) {
+        double av[8], bv[8];  // the b columns of this G in the block: at most 32
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int c = bc0 + 4 * s + kk;
+          const bool ok = c < bc1;
+          av[s] = (ok && a0 + l16 < na) ? Pb[(long long)(al * na + a0 + l16) * BN + (c - c0)] : 0.0;
+          bv[s] = (ok && g0 + l16 < ng) ? Yj[((long long)al * nb + (c - gb)) * ng + g0 + l16] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          if (bc0 + 4 * s < bc1) {
+            h = mfma64(av[s], bv[s], h);
+            ++nm;
+          }
+      }
+      for (int e = 0; e < 4; ++e) {
+        const int a = a0 + kk + 4 * e, g = g0 + l16;
+        if (a < na && g < ng && h[e] != 0.0) atomicAdd(S + a * ng + g, -h[e]);
+      }
+    }
+  return nm;
+}
+
+// ---------------------------------------------------------------------------------------------
 // GEMM-L: terms 1 and 2.  Rows (alpha,a), K = (F,f), columns (G, [g | b]).
 //   P[(al,a)][(G,g)] = sum_{F,f} C_AF[al][a][f] w D_FG[f][g]   (term 1, kept units only)
 //   P[(al,a)][(G,b)] = sum_{F,f} C_AF[al][a][f] w D_FB[f][b]   (term 2, kept units only)
@@ -907,7 +990,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
                              const short *col2jj, double *As, double *Bs, double *wg, int rows_cap,
                              long long *kaddr /* LDS [rows_cap] */, const float *ub, int tier, float tau) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
-  const int M = L.PA * L.na, na = L.na, nb = L.nb, nF = L.nF, PA = L.PA;
+  const int M = L.PA * L.na, nb = L.nb, nF = L.nF;
   const int ncb = (L.NR + BN - 1) / BN, nrb = (M + BM - 1) / BM;
   double *panel = wg;                                   // [rows_cap][64]
   double *Pb = panel + (long long)rows_cap * BN;        // [M][64]
@@ -1049,63 +1132,10 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
     __threadfence_block();
     __syncthreads();
     // contractions with Y: work items (target, alpha part); target 0 = term 1, 1+q = term 2 of jj0+q
-    const unsigned long long t2m = L.t2any;
-    const int nt2 = jj1 - jj0 + 1;
-    const int parts = NW;
-    const int nwork = (L.t1any ? parts : 0) + nt2;
-    for (int wi = wave; wi < nwork; wi += NW) {
-      const bool is1 = L.t1any && wi < parts;
-      if (is1) {
-        const int al0 = wi * PA / parts, al1 = (wi + 1) * PA / parts;
-        for (int a0 = 0; a0 < na; a0 += 16)
-          for (int b0 = 0; b0 < nb; b0 += 16) {
-            d4 h = {0, 0, 0, 0};
-            for (int al = al0; al < al1; ++al)
-              for (int cg = 0; cg < c1 - c0; cg += 4) {
-                const int cl = cg + kk, c = c0 + cl;
-                double av = 0.0, bv = 0.0;
-                if (c < c1) {
-                  const int jj = col2jj[c], j = L.a_j[jj];
-                  const int cc = c - L.a_col0[jj], ng = L.g_n[j];
-                  if (cc < ng) {
-                    if (a0 + l16 < na) av = Pb[(long long)(al * na + a0 + l16) * BN + cl];
-                    if (b0 + l16 < nb) bv = slot[L.a_y[jj] + ((long long)al * nb + b0 + l16) * ng + cc];
-                  }
-                }
-                h = mfma64(av, bv, h);
-              }
-            nmfma += (unsigned long long)(al1 - al0) * ((c1 - c0 + 3) >> 2);
-            for (int e = 0; e < 4; ++e) {
-              const int a = a0 + kk + 4 * e, b = b0 + l16;
-              if (a < na && b < nb && h[e] != 0.0) atomicAdd(&L.H1[a * MAXN + b], h[e]);
-            }
-          }
-      } else {
-        const int q = wi - (L.t1any ? parts : 0);
-        if (!((t2m >> q) & 1ull)) continue;
-        const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
-        const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
-        const int bc0 = max(c0, gb), bc1 = min(c1, g1);
-        for (int a0 = 0; a0 < na; a0 += 16)
-          for (int g0 = 0; g0 < ng; g0 += 16) {
-            d4 h = {0, 0, 0, 0};
-            for (int al = 0; al < PA; ++al)
-              for (int cbb = bc0; cbb < bc1; cbb += 4) {
-                const int c = cbb + kk;
-                double av = 0.0, bv = 0.0;
-                if (c < bc1) {
-                  if (a0 + l16 < na) av = Pb[(long long)(al * na + a0 + l16) * BN + (c - c0)];
-                  if (g0 + l16 < ng) bv = slot[L.a_y[jj] + ((long long)al * nb + (c - gb)) * ng + g0 + l16];
-                }
-                h = mfma64(av, bv, h);
-              }
-            nmfma += (unsigned long long)PA * ((bc1 - bc0 + 3) >> 2);
-            for (int e = 0; e < 4; ++e) {
-              const int a = a0 + kk + 4 * e, g = g0 + l16;
-              if (a < na && g < ng && h[e] != 0.0) atomicAdd(P.Sbuf + L.g_dAGoff[j] + a * ng + g, -h[e]);
-            }
-          }
-      }
+    {
+      const int nwork = (L.t1any ? NW : 0) + (jj1 - jj0 + 1);
+      for (int wi = wave; wi < nwork; wi += NW)
+        nmfma += ycontract_wave(L, col2jj, Pb, slot, P.Sbuf, wi, c0, c1, jj0, L.t2any, L.t1any != 0);
     }
     __syncthreads();
   }
