@@ -1,11 +1,13 @@
 """Benchmark: one HFX build (Sigma^X of a 512-atom Si-like supercell) per step.
 
     python bench.py [--steps K] [--warmup W] [--eps 1e-6] [--precision fp64|tiered|fp32 [--tau T]] [--graph]
+                    [--mixed-steps M]
 
 Workload: 4x4x4 conventional diamond cells (512 atoms, a = 10.26 bohr), 13 AOs / 60 ABFs
 per atom, C within 16 bohr, screened V (omega = 0.11/bohr), all five thresholds = eps.
 Inputs are seeded synthetic blocks (hfx_synth), resident in HBM before the timed
-region.  Prints one JSON line.
+region.  Prints one JSON line; after an FP64 run it also times the tiered FP32/FP64 form on
+the same inputs ("mixed": build time, speedup and errors against the FP64 build).
 """
 from __future__ import annotations
 
@@ -72,6 +74,40 @@ def measured_traffic(eps: float):
         return None
 
 
+def mixed_form(w, D, sigma64, e64, ms64, args):
+    """The tiered FP32/FP64 form on the same inputs: its build time and its Sigma / E_x against
+    the FP64 build just timed."""
+    import torch
+    from paper_2009_12505_amd import PREC_TIERED, Plan
+    torch.cuda.empty_cache()
+    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=PREC_TIERED, tier_tau=args.tau)
+    sigma = plan.alloc_sigma()
+    plan.build(D, sigma, stats=True)
+    progress(f"tiered warmup build: {plan.last_stats['ms_main']:.1f} ms")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.mixed_steps):
+        plan.build(D, sigma, stats=True)
+        progress(f"tiered timed build: {plan.last_stats['ms_main']:.1f} ms")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.mixed_steps
+    st = plan.last_stats
+    e = plan.energy(D, sigma)[0]
+    dsig = max(float((a - b).abs().max()) for a, b in zip(sigma, sigma64))
+    n_atoms = w.cells[0].n_atoms
+    fl = st["flops_contract"]
+    out = {"precision": "tiered", "tier_tau": args.tau, "steps": args.mixed_steps, "build_s": round(ms / 1e3, 4),
+           "speedup_vs_fp64": round(ms64 / ms, 4),
+           "flops_fp32_share": round(st["flops_tier"][1] / fl, 4) if fl > 0 else 0.0,
+           "max_abs_dsigma_vs_fp64": dsig, "de_x_per_atom_vs_fp64": abs(e - e64) / n_atoms}
+    del plan, sigma
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +118,9 @@ def main():
     ap.add_argument("--tau", type=float, default=1e-3, help="tier bound of the tiered form")
     ap.add_argument("--graph", action="store_true",
                     help="replay the build as one captured HIP graph (kernel time = whole graph)")
+    ap.add_argument("--mixed-steps", type=int, default=1,
+                    help="after an FP64 run: time this many builds of the tiered form (tau = --tau) on the "
+                         "same inputs and report them against the FP64 build (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -175,6 +214,9 @@ def main():
         "phase_share": st["phase_share"], "plan_s": round(t_plan, 2), "gen_s": round(t_gen, 2),
         "wall_s_timed": round(t_wall, 3),
     }
+    if args.precision == "fp64" and args.mixed_steps > 0:
+        del plan
+        out["mixed"] = mixed_form(w, D, sigma, e_x, ms_step, args)
     if not args.no_cpu_baseline:
         nt = args.cpu_threads or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(args.eps, fl_paper / n_atoms, nt)

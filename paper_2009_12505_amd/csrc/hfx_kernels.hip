@@ -696,41 +696,50 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned 
   }
 }
 
-// The same block product on the FP32 matrix cores (v_mfma_f32_16x16x4f32), same chunking:
-// operands are fetched as (or converted to) FP32, so the stages and the A operand traffic
-// are half those of the FP64 form and each MFMA takes half the matrix-core time.
+// The same block product on the FP32 matrix cores (v_mfma_f32_16x16x4f32), BKF K per chunk.
+// Thread tid fetches BKF/4 A elements (row tid&127, k rows (BKF/4)*(tid>>7)..) and BKF/8 B
+// elements (column tid&63, k rows tid>>6 + 8q) per chunk.  B arrives in FP64 (T3/T4, the
+// D panel) and is rounded only when it is stored into the stage: rounded at the fetch, the
+// conversion makes the wave wait for the load there, and the next chunk's loads no longer
+// overlap the current chunk's MFMAs.  (32-K FP32 chunks fit the same LDS; measured no faster
+// and they spill more registers.)
+constexpr int BKF = 16;
+static_assert(BKF * (BM + BN) * 4 <= BK * (BM + BN) * 8, "FP32 stages reuse the FP64 stage buffers");
+
 template <class AAt, class BAt>
 __device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, unsigned act, float *As, float *Bs,
                                               f4 (&acc)[4]) {
+  constexpr int NA = BKF / 4, NB = BKF / 8;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
-  const int ar = tid & (BM - 1), akq = (tid >> 7) << 2;
+  const int ar = tid & (BM - 1), akq = (tid >> 7) * NA;
   const int bc = tid & (BN - 1), bk = tid >> 6;
-  float ra[4], rb[2];
+  float ra[NA];
+  double rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0f;
-    rb[0] = k0 + bk < K ? b_at(k0 + bk) : 0.0f;
-    rb[1] = k0 + bk + 8 < K ? b_at(k0 + bk + 8) : 0.0f;
+    for (int s = 0; s < NA; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0f;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) rb[q] = k0 + bk + 8 * q < K ? b_at(k0 + bk + 8 * q) : 0.0;
   };
   auto stash = [&](int st) {
-    float *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+    float *a = As + st * BKF * BM, *b = Bs + st * BKF * BN;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = ra[s];
-    b[bk * BN + bc] = rb[0];
-    b[(bk + 8) * BN + bc] = rb[1];
+    for (int s = 0; s < NA; ++s) a[(akq + s) * BM + ar] = ra[s];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) b[(bk + 8 * q) * BN + bc] = (float)rb[q];
   };
   __syncthreads();  // the previous user of the stages is done
   fetch(0);
   stash(0);
   __syncthreads();
   int st = 0;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const bool more = k0 + BK < K;
-    if (more) fetch(k0 + BK);
+  for (int k0 = 0; k0 < K; k0 += BKF) {
+    const bool more = k0 + BKF < K;
+    if (more) fetch(k0 + BKF);
     if (act) {
-      const float *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+      const float *a = As + st * BKF * BM, *b = Bs + st * BKF * BN;
 #pragma unroll 2
-      for (int s = 0; s < BK / 4; ++s) {
+      for (int s = 0; s < BKF / 4; ++s) {
         const int kr = 4 * s + kk;
         const float av = a[kr * BM + wave * 16 + l16];
 #pragma unroll
@@ -837,7 +846,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
         for (int v = 0; v < 4; ++v) a32[v] = f4{0, 0, 0, 0};
         wg_block_mm32(
             K, [&](int k) { return rok ? Ab32[(long long)k * As_] : 0.0f; },
-            [&](int k) { return cok ? (float)Bb[(long long)k * Bstr] : 0.0f; }, act, reinterpret_cast<float *>(As),
+            [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, reinterpret_cast<float *>(As),
             reinterpret_cast<float *>(Bs), a32);
         nmfma32 += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
 #pragma unroll
@@ -1102,7 +1111,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
               const long long ka = kaddr[k];
               return (rok && ka >= 0) ? CT32[ka + r] : 0.0f;
             },
-            [&](int k) { return (float)panel[(long long)k * BN + bcl]; }, act, reinterpret_cast<float *>(As),
+            [&](int k) { return panel[(long long)k * BN + bcl]; }, act, reinterpret_cast<float *>(As),
             reinterpret_cast<float *>(Bs), a32);
         nmfma32 += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
 #pragma unroll

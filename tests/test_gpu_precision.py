@@ -64,3 +64,11 @@ def test_cfg3_eps1e4_tiered_vs_primitive():
     """The 512-atom supercell with the tiered form meets the method's target against the oracle."""
     from paper_2009_12505_amd import PREC_TIERED
     _supercell_vs_primitive("cfg3", 1e-4, 1e-9, precision=PREC_TIERED, tier_tau=TAU)
+
+
+@pytest.mark.timeout(900)
+def test_cfg3_eps1e6_tiered_vs_primitive():
+    """The benchmark workload (512 atoms, eps 1e-6) in the tiered form bench.py also times:
+    every Sigma block against the oracle's primitive-cell block of the same atom pair."""
+    from paper_2009_12505_amd import PREC_TIERED
+    _supercell_vs_primitive("cfg3", 1e-6, 1e-9, precision=PREC_TIERED, tier_tau=TAU)
