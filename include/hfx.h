@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define HFX_ABI_VERSION 1
+#define HFX_ABI_VERSION 2
 
 typedef enum {
   HFX_OK = 0,
@@ -207,47 +207,58 @@ hfx_status hfx_build(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, 
  * e_x: n_cells host doubles.  Synchronises. */
 hfx_status hfx_energy(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, double *e_x);
 
-/* Per-item cost labels of the last build, for scheduler training: for each
- * work item in plan order, its main-kernel wall-clock ticks (100 MHz) and
- * five counters the kernel produced: kept units of terms 1..4 after stage 3
- * and the number of G whose Y = V C was formed.  cycles: n_items int64,
- * units: n_items*5 int64 (host); either may be NULL.  Synchronises. */
-hfx_status hfx_item_profile(hfx_plan *plan, int64_t *n_items, int64_t *cycles, int64_t *units);
+/* Per-item labels of the last build, for scheduler training: for each work
+ * item in plan order, its main-kernel wall-clock ticks (100 MHz), five
+ * counters the kernel produced (kept units of terms 1..4 after stage 3 and
+ * the number of G whose Y = V C was formed) and its contribution bound: the
+ * sum over its kept units of the tightest screening bound the kernel computed
+ * for the unit (the stage-3 bound of Sec. III C 2 where stage 3 runs, else
+ * the stage-2 bound), an upper bound of the Frobenius norm of the item's
+ * contribution to Sigma.  cycles: n_items int64, units: n_items*5 int64,
+ * contrib: n_items doubles (host); any may be NULL.  Synchronises. */
+hfx_status hfx_item_profile(hfx_plan *plan, int64_t *n_items, int64_t *cycles, int64_t *units, double *contrib);
 
-/* Learned cost model of the scheduler (the greedy longest-first machine
+/* Learned model of the scheduler (the greedy longest-first machine
  * scheduling of Sec. III D 1, Algorithm 6, applied to predicted instead of
- * static costs): a perceptron x -> tanh(W1 x + b1) -> tanh(W2 h + b2) -> w3 . h + b3
- * with n_in inputs and n_hidden units per hidden layer; FP32 parameters laid
- * out as W1[n_hidden][n_in], b1, W2[n_hidden][n_hidden], b2, w3, b3.
- * All arrays are device memory; stream as in hfx_options.  The model never
- * changes which units are computed, only the order in which items run.
- * Errors: HFX_ERR_ARG for n_in outside 1..16, n_hidden outside 1..64, NULL
- * arrays, n < 0, epochs < 0 or lr <= 0; HFX_ERR_OOM if the optimizer state
- * cannot be allocated; HFX_ERR_HIP if a launch fails.                      */
-int64_t hfx_mlp_n_params(int32_t n_in, int32_t n_hidden);
+ * static costs): a perceptron x -> tanh(W1 x + b1) -> tanh(W2 h + b2) -> W3 h + b3
+ * with n_in inputs, n_hidden units per hidden layer and n_out linear outputs;
+ * FP32 parameters laid out as W1[n_hidden][n_in], b1, W2[n_hidden][n_hidden],
+ * b2, W3[n_out][n_hidden], b3[n_out].  The scheduler's model has two outputs:
+ * log(cycles) and log of the contribution bound (hfx_item_profile), each
+ * standardised by the trainer.  All arrays are device memory; stream as in
+ * hfx_options.  The model never changes which units are computed, only the
+ * order in which items run.
+ * Errors: HFX_ERR_ARG for n_in outside 1..16, n_hidden outside 1..64, n_out
+ * outside 1..4, NULL arrays, n < 0, epochs < 0 or lr <= 0; HFX_ERR_OOM if the
+ * optimizer state cannot be allocated; HFX_ERR_HIP if a launch fails. */
+int64_t hfx_mlp_n_params(int32_t n_in, int32_t n_hidden, int32_t n_out);
 
-/* y[i] = model(X[i*n_in ..]) for n samples. */
-hfx_status hfx_mlp_predict(int32_t n_in, int32_t n_hidden, const float *params, const float *X, int64_t n, float *y,
-                           void *stream);
+/* y[i*n_out + o] = output o of the model at X[i*n_in ..], for n samples. */
+hfx_status hfx_mlp_predict(int32_t n_in, int32_t n_hidden, int32_t n_out, const float *params, const float *X,
+                           int64_t n, float *y, void *stream);
 
-/* loss = mean (model(X_i) - t_i)^2 and grad = d loss / d params (overwritten). */
-hfx_status hfx_mlp_loss_grad(int32_t n_in, int32_t n_hidden, const float *params, const float *X, const float *t,
-                             int64_t n, float *grad, float *loss, void *stream);
+/* loss = mean over samples of sum_o (y_io - t_io)^2 (t: n x n_out) and
+ * grad = d loss / d params (overwritten). */
+hfx_status hfx_mlp_loss_grad(int32_t n_in, int32_t n_hidden, int32_t n_out, const float *params, const float *X,
+                             const float *t, int64_t n, float *grad, float *loss, void *stream);
 
-/* Full-batch Adam on the mean squared error for `epochs` steps (params
- * updated in place); loss_host (host, epochs floats, optional) receives the
- * loss before each step.  Allocates its optimizer state.  Synchronises. */
-hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, float *params, const float *X, const float *t, int64_t n,
-                         int32_t epochs, float lr, float *loss_host, void *stream);
+/* Full-batch Adam on that loss for `epochs` steps (params updated in place);
+ * loss_host (host, epochs floats, optional) receives the loss before each
+ * step.  Allocates its optimizer state.  Synchronises. */
+hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, int32_t n_out, float *params, const float *X, const float *t,
+                         int64_t n, int32_t epochs, float lr, float *loss_host, void *stream);
 
-/* The scheduler's 8 input features of every work item, from the last
- * build's counters: log1p(kept units of terms 1..4), log1p(G formed),
- * log(|N(A)| |N(B)|), n_ao(A)/16, n_abf(A)/64, each normalised as
- * (x - mu[k]) / sd[k] (mu, sd: 8 host floats).  X: device, n_items*8 floats.
- * A plan created with HFX_SCHED_MLP and a model file (mlp_weights: "HFXMLP01",
- * int32 n_in = 8, int32 n_hidden, float mu[8], float sd[8], float params[...])
- * orders each build's items by the model applied to these features of the
- * previous build (its first build uses HFX_SCHED_LPT order).  Synchronises. */
+/* The scheduler's 10 input features of every work item: from the last
+ * build's counters log1p(kept units of terms 1..4), log1p(G formed); from the
+ * plan log(|N(A)| |N(B)|), n_ao(A)/16, n_abf(A)/64, the pair distance
+ * |r_B + R - r_A| / 10 bohr and log(atoms of the item's cell); each
+ * normalised as (x - mu[k]) / sd[k] (mu, sd: 10 host floats).  X: device,
+ * n_items*10 floats.  A plan created with HFX_SCHED_MLP and a model file
+ * (mlp_weights: "HFXMLP02", int32 n_in = 10, int32 n_hidden, int32 n_out,
+ * float mu[10], float sd[10], float params[...], then any trailing data,
+ * which the library does not read) orders each build's items by
+ * output 0 of the model applied to these features of the previous build (its
+ * first build uses HFX_SCHED_LPT order).  Synchronises. */
 hfx_status hfx_item_features(hfx_plan *plan, const float *mu, const float *sd, float *X);
 
 void hfx_plan_destroy(hfx_plan *plan);

@@ -21,6 +21,9 @@ EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "h
             "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",
             "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features"]
 ITEM_UNITS = 5
+ITEM_FEATURES = 10
+ITEM_TARGETS = 2
+ABI_VERSION = 2
 
 
 class Species(ctypes.Structure):
@@ -98,7 +101,7 @@ def lib():
         L.hfx_energy.restype = ctypes.c_int
         L.hfx_energy.argtypes = [P, P, P, P]
         L.hfx_item_profile.restype = ctypes.c_int
-        L.hfx_item_profile.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P, P]
+        L.hfx_item_profile.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P, P, P]
         L.hfx_plan_destroy.restype = None
         L.hfx_plan_destroy.argtypes = [P]
         L.hfx_last_error.restype = ctypes.c_char_p
@@ -106,16 +109,20 @@ def lib():
         L.hfx_abi_version.restype = ctypes.c_int32
         L.hfx_abi_version.argtypes = []
         L.hfx_mlp_n_params.restype = ctypes.c_int64
-        L.hfx_mlp_n_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.hfx_mlp_n_params.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.hfx_mlp_predict.restype = ctypes.c_int
-        L.hfx_mlp_predict.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64, P, P]
+        L.hfx_mlp_predict.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64, P, P]
         L.hfx_mlp_loss_grad.restype = ctypes.c_int
-        L.hfx_mlp_loss_grad.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, P, P, P]
+        L.hfx_mlp_loss_grad.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, P, P,
+                                        P]
         L.hfx_mlp_train.restype = ctypes.c_int
-        L.hfx_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, ctypes.c_int32,
+        L.hfx_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_float, P, P]
         L.hfx_item_features.restype = ctypes.c_int
         L.hfx_item_features.argtypes = [P, P, P, P]
+        if L.hfx_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.hfx_abi_version()}, this binding expects "
+                              f"{ABI_VERSION}: rebuild it with `python -m paper_2009_12505_amd.build`")
         _lib = L
     return _lib
 

@@ -82,6 +82,7 @@ struct DevPlan {
   double *flops;                 // [0] Algorithm-3 count, [1] this kernel's useful count
   long long *item_cycles;        // per item (plan order)
   int *item_units;               // per item x kItemUnits
+  double *item_contrib;          // per item: summed screening bounds of its kept units
 };
 
 enum {
@@ -99,6 +100,8 @@ enum {
 };
 
 constexpr int kItemUnits = 5;  // per item: kept units of terms 1..4, alive G
+constexpr int kItemFeatures = 10;  // scheduler model inputs per item
+constexpr int kItemTargets = 2;   // scheduler model outputs: log cycles, log contribution bound
 
 constexpr uint32_t kPre = 1u, kCsEri = 2u, kCs1 = 4u, kCs2 = 8u, kCs3 = 16u;
 

@@ -114,6 +114,7 @@ struct ItemLds {
   int fsrow[MAXNB + 1];
   unsigned long long cnt[kCntN];
   double flops[2];
+  double contrib;  // summed screening bounds of the item's kept units
   int scratch_top;
 };
 
@@ -447,6 +448,9 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
   const double eps = P.eps_mat;
   const bool use2 = P.stages & kCs2, use3 = P.stages & kCs3;
   unsigned long long c2[4] = {0, 0, 0, 0}, c3[4] = {0, 0, 0, 0}, nm = 0;
+  // the tightest bound of every kept unit (stage 3 where it runs, else stage 2), summed: an
+  // upper bound of the Frobenius norm of the item's contribution to Sigma (weights <= 1)
+  double cb = 0.0;
   // E2_i = D_FB^T D_FB  [b][b']  (one wave per F)
   for (int i = wave; i < nF; i += NW) {
     double *E = E2 + (long long)i * nb * nb;
@@ -477,42 +481,62 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       continue;
     }
     if (bits & kT1) {
-      if (!use2 || L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]] > eps) {
+      const double b = L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]];
+      if (!use2 || b > eps) {
         ++c2[0];
-        if (use3)
+        if (use3) {
           bits |= kPend1;
-        else
+        } else {
           ++c3[0];
+          cb += b;
+        }
       } else {
         bits &= ~kT1;
       }
     }
     if (bits & kT2) {
-      if (!use2 || L.f_gA[i] * L.a_Yg[jj] * P.gD[L.f_dFB[i]] > eps) {
+      const double b = L.f_gA[i] * L.a_Yg[jj] * P.gD[L.f_dFB[i]];
+      if (!use2 || b > eps) {
         ++c2[1];
-        if (use3)
+        if (use3) {
           bits |= kPend2;
-        else
+        } else {
           ++c3[1];
+          cb += b;
+        }
       } else {
         bits &= ~kT2;
       }
     }
     if (bits & kT3) {
-      bool keep = !use2 || L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]] > eps;
+      double b = L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]];
+      bool keep = !use2 || b > eps;
       if (keep) {
         ++c2[2];
-        if (use3) keep = L.f_nF[i] * L.a_T3n[jj] > eps;
-        if (keep) ++c3[2];
+        if (use3) {
+          b = L.f_nF[i] * L.a_T3n[jj];
+          keep = b > eps;
+        }
+        if (keep) {
+          ++c3[2];
+          cb += b;
+        }
       }
       if (!keep) bits &= ~kT3;
     }
     if (bits & kT4) {
-      bool keep = !use2 || L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB] > eps;
+      double b = L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB];
+      bool keep = !use2 || b > eps;
       if (keep) {
         ++c2[3];
-        if (use3) keep = L.f_nF[i] * L.a_T4n[jj] > eps;
-        if (keep) ++c3[3];
+        if (use3) {
+          b = L.f_nF[i] * L.a_T4n[jj];
+          keep = b > eps;
+        }
+        if (keep) {
+          ++c3[3];
+          cb += b;
+        }
       }
       if (!keep) bits &= ~kT4;
     }
@@ -557,9 +581,13 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
           const int q = ii * nG + j;
           const uint8_t bits = mask[q];
           if (bits & kPend2) {
-            const bool keep = L.f_nA[ii] * sqrt(fmax(v, 0.0)) > eps;
+            const double b = L.f_nA[ii] * sqrt(fmax(v, 0.0));
+            const bool keep = b > eps;
             mask[q] = keep ? (uint8_t)(bits & ~kPend2) : (uint8_t)(bits & ~(kPend2 | kT2));
-            if (keep) ++c3[1];
+            if (keep) {
+              ++c3[1];
+              cb += b;
+            }
           }
         }
       }
@@ -621,9 +649,13 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
             const int i = fl[r];
             const int q = i * nG + j;
             const uint8_t bits = mask[q];
-            const bool keep = L.f_nA[i] * sqrt(fmax(v, 0.0)) > eps;
+            const double b = L.f_nA[i] * sqrt(fmax(v, 0.0));
+            const bool keep = b > eps;
             mask[q] = keep ? (uint8_t)(bits & ~kPend1) : (uint8_t)(bits & ~(kPend1 | kT1));
-            if (keep) ++c3[0];
+            if (keep) {
+              ++c3[0];
+              cb += b;
+            }
           }
         }
         __threadfence_block();
@@ -634,6 +666,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
     if (c2[t]) atomicAdd(&L.cnt[kCntKept + 4 + t], c2[t]);
     if (c3[t]) atomicAdd(&L.cnt[kCntKept + 8 + t], c3[t]);
   }
+  if (cb != 0.0) atomicAdd(&L.contrib, cb);
   if (lane == 0 && nm) atomicAdd(&L.cnt[kCntMfmaY], nm);
 }
 
@@ -1177,6 +1210,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     if (tid < kCntN) L.cnt[tid] = 0;
     if (tid < 2) L.flops[tid] = 0.0;
     if (tid == 0) {
+      L.contrib = 0.0;
       L.A = it.A;
       L.B = it.B;
       L.rb = it.rb;
@@ -1387,7 +1421,10 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     if (tid < 2 && L.flops[tid] != 0.0) atomicAdd(&P.flops[tid], L.flops[tid]);
     if (tid < 4) P.item_units[item * kItemUnits + tid] = (int)L.cnt[kCntKept + 8 + tid];
     if (tid == 4) P.item_units[item * kItemUnits + 4] = L.nGa;
-    if (tid == 0) P.item_cycles[item] = wall_clock64() - t_start;
+    if (tid == 0) {
+      P.item_cycles[item] = wall_clock64() - t_start;
+      P.item_contrib[item] = L.contrib;
+    }
     __syncthreads();
   }
 }

@@ -49,16 +49,18 @@ hipError_t launch_dmax(const double *gD, const uint8_t *keepD, const long long *
                        hipStream_t s);
 hipError_t launch_reset(unsigned int *ticket, unsigned long long *counters, double *flops, hipStream_t s);
 hipError_t launch_energy(const double *D, const double *S, long long n, double *part, int nblk, hipStream_t s);
-hipError_t mlp_launch_predict(const float *P, int F, int H, const float *X, long long n, float *out, hipStream_t s);
-hipError_t mlp_launch_grad(const float *P, int F, int H, const float *X, const float *T, long long n, float *G,
+hipError_t mlp_launch_predict(const float *P, int F, int H, int O, const float *X, long long n, float *out,
+                              hipStream_t s);
+hipError_t mlp_launch_grad(const float *P, int F, int H, int O, const float *X, const float *T, long long n, float *G,
                            float *loss, hipStream_t s);
 hipError_t mlp_launch_adam(float *P, const float *G, float *m, float *v, int np, float lr, int step, hipStream_t s);
 hipError_t mlp_launch_features(const Item *items, const int *units, const int *c_start, const int *nao,
-                               const int *nabf, long long n, const float *mu, const float *sd, float *X,
-                               hipStream_t s);
-int64_t mlp_params(int F, int H);
+                               const int *nabf, const float *dist, const int *cell_of, const int *cell_natoms,
+                               long long n, const float *mu, const float *sd, float *X, hipStream_t s);
+int64_t mlp_params(int F, int H, int O);
 int mlp_max_h();
 int mlp_max_f();
+int mlp_max_o();
 }  // namespace hfx
 
 using namespace hfx;
@@ -140,7 +142,9 @@ struct hfx_plan {
   double *part = nullptr;  // energy partial sums
   // learned scheduler
   bool have_profile = false;
-  int mlp_f = 0, mlp_h = 0;
+  int mlp_f = 0, mlp_h = 0, mlp_o = 0;
+  std::vector<float> item_dist;    // |r_B + R - r_A| of every item (bohr)
+  float *item_dist_dev = nullptr;
   float *feat_musd = nullptr;  // normalisation for hfx_item_features
   float *mlp_params_dev = nullptr, *mlp_mu = nullptr, *mlp_sd = nullptr, *mlp_X = nullptr, *mlp_y = nullptr;
   std::vector<int32_t> lpt_order;
@@ -524,6 +528,18 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     if (nF == 0 || nG == 0) continue;
     p->items.push_back(Item{A, B, v_Rp[vb], vb});
     cost.push_back((double)nF * nG);
+    {
+      const hfx_cell &cl = cells[p->cell_of[A]];
+      const int la = p->local_of[A], lb = p->local_of[B];
+      const int32_t rp = v_Rp[vb];
+      double d2 = 0.0;
+      for (int x = 0; x < 3; ++x) {
+        const double dx = cl.pos[3 * lb + x] - cl.pos[3 * la + x] + r_of(rp, 0) * cl.lattice[x] +
+                          r_of(rp, 1) * cl.lattice[3 + x] + r_of(rp, 2) * cl.lattice[6 + x];
+        d2 += dx * dx;
+      }
+      p->item_dist.push_back((float)std::sqrt(d2));
+    }
   }
   p->n_items = (int64_t)p->items.size();
   p->order.resize(p->n_items);
@@ -656,6 +672,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   double *d_flops = nullptr;
   long long *d_icyc = nullptr;
   int *d_iunits = nullptr;
+  double *d_icontrib = nullptr;
   std::vector<int32_t> ord32(p->order.begin(), p->order.end());
   if ((st = p->upload(&d_nao, p->nao)) || (st = p->upload(&d_nabf, p->nabf)) ||
       (st = p->upload(&d_cellof, p->cell_of)) || (st = p->upload(&d_localof, p->local_of)) ||
@@ -674,6 +691,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       (st = p->dalloc(&d_keepD, (size_t)p->nD)) || (st = p->upload(&d_items, p->items)) ||
       (st = p->upload(&d_order, ord32)) || (st = p->dalloc(&d_ticket, 1)) || (st = p->dalloc(&d_cnt, kCntN)) ||
       (st = p->dalloc(&d_flops, 2)) || (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * kItemUnits)) ||
+      (st = p->dalloc(&d_icontrib, (size_t)p->n_items)) || (st = p->upload(&p->item_dist_dev, p->item_dist)) ||
       (st = p->dalloc(&d_scr, (size_t)p->n_slots * slot)) || (st = p->dalloc(&p->part, 2 * p->part_blocks)))
     return st;
   cstage.clear();
@@ -739,12 +757,14 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   P.flops = d_flops;
   P.item_cycles = d_icyc;
   P.item_units = d_iunits;
+  P.item_contrib = d_icontrib;
 
   {
     const void *must[] = {P.nao, P.nabf, P.cell_of, P.local_of, P.Cbuf, P.CTbuf, P.c_off, P.c_col, P.c_R, P.c_norm,
                           P.c_start, P.Vbuf, P.v_off, P.gV, P.ptab_off, P.pstart, P.pcount, P.dsort_R, P.dsort_id,
                           P.cell_natoms, P.d_off, P.Dbuf, P.gD, P.keepD, P.gDmax, P.Sbuf, P.items, P.order,
-                          P.scratch, P.ticket, P.counters, P.flops, P.item_cycles, P.item_units, p->part,
+                          P.scratch, P.ticket, P.counters, P.flops, P.item_cycles, P.item_units, P.item_contrib,
+                          p->item_dist_dev, p->part,
                           p->d_row_dev, p->d_col_dev, p->dbase_dev};
     for (const void *q : must)
       if (!q) return fail(HFX_ERR_OOM, "internal: a device buffer of the plan was not allocated");
@@ -756,14 +776,15 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     FILE *fp = std::fopen(o.mlp_weights, "rb");
     if (!fp) return fail(HFX_ERR_ARG, "cannot open mlp_weights '%s'", o.mlp_weights);
     char magic[8];
-    int32_t fh[2];
-    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "HFXMLP01", 8) == 0 &&
-              std::fread(fh, sizeof(int32_t), 2, fp) == 2 && fh[0] == 8 && fh[1] >= 1 && fh[1] <= mlp_max_h();
+    int32_t fh[3];
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "HFXMLP02", 8) == 0 &&
+              std::fread(fh, sizeof(int32_t), 3, fp) == 3 && fh[0] == kItemFeatures && fh[1] >= 1 &&
+              fh[1] <= mlp_max_h() && fh[2] >= 1 && fh[2] <= mlp_max_o();
     std::vector<float> mu, sd, prm;
     if (ok) {
       mu.resize(fh[0]);
       sd.resize(fh[0]);
-      prm.resize((size_t)mlp_params(fh[0], fh[1]));
+      prm.resize((size_t)mlp_params(fh[0], fh[1], fh[2]));
       ok = std::fread(mu.data(), sizeof(float), mu.size(), fp) == mu.size() &&
            std::fread(sd.data(), sizeof(float), sd.size(), fp) == sd.size() &&
            std::fread(prm.data(), sizeof(float), prm.size(), fp) == prm.size();
@@ -772,9 +793,10 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     if (!ok) return fail(HFX_ERR_ARG, "mlp_weights '%s' is not a scheduler model file", o.mlp_weights);
     p->mlp_f = fh[0];
     p->mlp_h = fh[1];
+    p->mlp_o = fh[2];
     if ((st = p->upload(&p->mlp_params_dev, prm)) || (st = p->upload(&p->mlp_mu, mu)) ||
         (st = p->upload(&p->mlp_sd, sd)) || (st = p->dalloc(&p->mlp_X, (size_t)p->n_items * fh[0])) ||
-        (st = p->dalloc(&p->mlp_y, (size_t)p->n_items)))
+        (st = p->dalloc(&p->mlp_y, (size_t)p->n_items * fh[2])))
       return st;
   }
   // ---- plan-time kernels: C norms, CS-ERI factors, V norms
@@ -940,12 +962,14 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
   DevPlan &P = p->dp;
   if (p->scheduler == HFX_SCHED_MLP && p->have_profile && p->n_items > 0) {
     // learned costs from the previous build's per-item counters; longest predicted first
-    HIPCHK(p, mlp_launch_features(P.items, P.item_units, P.c_start, P.nao, P.nabf, p->n_items, p->mlp_mu, p->mlp_sd,
-                                  p->mlp_X, p->stream));
-    HIPCHK(p, mlp_launch_predict(p->mlp_params_dev, p->mlp_f, p->mlp_h, p->mlp_X, p->n_items, p->mlp_y, p->stream));
-    std::vector<float> pred(p->n_items);
-    HIPCHK(p, hipMemcpyAsync(pred.data(), p->mlp_y, pred.size() * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(p, mlp_launch_features(P.items, P.item_units, P.c_start, P.nao, P.nabf, p->item_dist_dev, P.cell_of,
+                                  P.cell_natoms, p->n_items, p->mlp_mu, p->mlp_sd, p->mlp_X, p->stream));
+    HIPCHK(p, mlp_launch_predict(p->mlp_params_dev, p->mlp_f, p->mlp_h, p->mlp_o, p->mlp_X, p->n_items, p->mlp_y,
+                                 p->stream));
+    std::vector<float> y((size_t)p->n_items * p->mlp_o), pred(p->n_items);
+    HIPCHK(p, hipMemcpyAsync(y.data(), p->mlp_y, y.size() * sizeof(float), hipMemcpyDeviceToHost, p->stream));
     HIPCHK(p, hipStreamSynchronize(p->stream));
+    for (int64_t i = 0; i < p->n_items; ++i) pred[i] = y[(size_t)i * p->mlp_o];  // output 0: log cost
     // longest predicted first, on a grid of 0.1 (predictions are standardised log times) so that
     // items of similar cost keep the plan order, which groups the items of one atom A and lets
     // concurrent workgroups share its C blocks in cache
@@ -1028,7 +1052,7 @@ hfx_status hfx_energy(hfx_plan *p, const hfx_blocks *D, double *const *sigma, do
   return HFX_OK;
 }
 
-hfx_status hfx_item_profile(hfx_plan *p, int64_t *n_items, int64_t *cycles, int64_t *units) {
+hfx_status hfx_item_profile(hfx_plan *p, int64_t *n_items, int64_t *cycles, int64_t *units, double *contrib) {
   if (!p || !n_items) return fail(HFX_ERR_ARG, "NULL argument");
   *n_items = p->n_items;
   if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
@@ -1043,6 +1067,8 @@ hfx_status hfx_item_profile(hfx_plan *p, int64_t *n_items, int64_t *cycles, int6
     HIPCHK(p, hipMemcpy(u.data(), p->dp.item_units, u.size() * sizeof(int), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < u.size(); ++i) units[i] = u[i];
   }
+  if (contrib && p->n_items)
+    HIPCHK(p, hipMemcpy(contrib, p->dp.item_contrib, (size_t)p->n_items * sizeof(double), hipMemcpyDeviceToHost));
   return HFX_OK;
 }
 
@@ -1051,53 +1077,55 @@ hfx_status hfx_item_features(hfx_plan *p, const float *mu, const float *sd, floa
   if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
   if (!p->have_profile) return fail(HFX_ERR_STATE, "item features need a completed build");
   hfx_status st;
-  if (!p->feat_musd && (st = p->dalloc(&p->feat_musd, 16))) return st;
-  float musd[16];
-  std::memcpy(musd, mu, 8 * sizeof(float));
-  std::memcpy(musd + 8, sd, 8 * sizeof(float));
+  if (!p->feat_musd && (st = p->dalloc(&p->feat_musd, 2 * kItemFeatures))) return st;
+  float musd[2 * kItemFeatures];
+  std::memcpy(musd, mu, kItemFeatures * sizeof(float));
+  std::memcpy(musd + kItemFeatures, sd, kItemFeatures * sizeof(float));
   HIPCHK(p, hipStreamSynchronize(p->stream));
   HIPCHK(p, hipMemcpy(p->feat_musd, musd, sizeof(musd), hipMemcpyHostToDevice));
-  HIPCHK(p, mlp_launch_features(p->dp.items, p->dp.item_units, p->dp.c_start, p->dp.nao, p->dp.nabf, p->n_items,
-                                p->feat_musd, p->feat_musd + 8, X, p->stream));
+  HIPCHK(p, mlp_launch_features(p->dp.items, p->dp.item_units, p->dp.c_start, p->dp.nao, p->dp.nabf,
+                                p->item_dist_dev, p->dp.cell_of, p->dp.cell_natoms, p->n_items, p->feat_musd,
+                                p->feat_musd + kItemFeatures, X, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
   return HFX_OK;
 }
 
-int64_t hfx_mlp_n_params(int32_t n_in, int32_t n_hidden) { return mlp_params(n_in, n_hidden); }
+int64_t hfx_mlp_n_params(int32_t n_in, int32_t n_hidden, int32_t n_out) { return mlp_params(n_in, n_hidden, n_out); }
 
-static hfx_status mlp_check(int32_t n_in, int32_t n_hidden, const void *a, const void *b, int64_t n) {
-  if (n_in < 1 || n_in > mlp_max_f() || n_hidden < 1 || n_hidden > mlp_max_h())
-    return fail(HFX_ERR_ARG, "n_in must be 1..%d and n_hidden 1..%d", mlp_max_f(), mlp_max_h());
+static hfx_status mlp_check(int32_t n_in, int32_t n_hidden, int32_t n_out, const void *a, const void *b, int64_t n) {
+  if (n_in < 1 || n_in > mlp_max_f() || n_hidden < 1 || n_hidden > mlp_max_h() || n_out < 1 || n_out > mlp_max_o())
+    return fail(HFX_ERR_ARG, "n_in must be 1..%d, n_hidden 1..%d and n_out 1..%d", mlp_max_f(), mlp_max_h(),
+                mlp_max_o());
   if (!a || !b || n < 0) return fail(HFX_ERR_ARG, "NULL argument or negative n");
   return HFX_OK;
 }
 
-hfx_status hfx_mlp_predict(int32_t n_in, int32_t n_hidden, const float *params, const float *X, int64_t n, float *y,
-                           void *stream) {
-  hfx_status st = mlp_check(n_in, n_hidden, params, X, n);
+hfx_status hfx_mlp_predict(int32_t n_in, int32_t n_hidden, int32_t n_out, const float *params, const float *X,
+                           int64_t n, float *y, void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, n_out, params, X, n);
   if (st) return st;
   if (!y) return fail(HFX_ERR_ARG, "NULL output");
-  if (mlp_launch_predict(params, n_in, n_hidden, X, n, y, (hipStream_t)stream) != hipSuccess)
+  if (mlp_launch_predict(params, n_in, n_hidden, n_out, X, n, y, (hipStream_t)stream) != hipSuccess)
     return fail(HFX_ERR_HIP, "predict launch failed: %s", hipGetErrorString(hipGetLastError()));
   return HFX_OK;
 }
 
-hfx_status hfx_mlp_loss_grad(int32_t n_in, int32_t n_hidden, const float *params, const float *X, const float *t,
-                             int64_t n, float *grad, float *loss, void *stream) {
-  hfx_status st = mlp_check(n_in, n_hidden, params, X, n);
+hfx_status hfx_mlp_loss_grad(int32_t n_in, int32_t n_hidden, int32_t n_out, const float *params, const float *X,
+                             const float *t, int64_t n, float *grad, float *loss, void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, n_out, params, X, n);
   if (st) return st;
   if (!t || !grad || !loss) return fail(HFX_ERR_ARG, "NULL argument");
-  if (mlp_launch_grad(params, n_in, n_hidden, X, t, n, grad, loss, (hipStream_t)stream) != hipSuccess)
+  if (mlp_launch_grad(params, n_in, n_hidden, n_out, X, t, n, grad, loss, (hipStream_t)stream) != hipSuccess)
     return fail(HFX_ERR_HIP, "gradient launch failed: %s", hipGetErrorString(hipGetLastError()));
   return HFX_OK;
 }
 
-hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, float *params, const float *X, const float *t, int64_t n,
-                         int32_t epochs, float lr, float *loss_host, void *stream) {
-  hfx_status st = mlp_check(n_in, n_hidden, params, X, n);
+hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, int32_t n_out, float *params, const float *X, const float *t,
+                         int64_t n, int32_t epochs, float lr, float *loss_host, void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, n_out, params, X, n);
   if (st) return st;
   if (!t || epochs < 0 || !(lr > 0)) return fail(HFX_ERR_ARG, "bad targets, epochs or learning rate");
-  const int np = (int)mlp_params(n_in, n_hidden);
+  const int np = (int)mlp_params(n_in, n_hidden, n_out);
   hipStream_t s = (hipStream_t)stream;
   float *buf = nullptr;
   if (hipMalloc(&buf, sizeof(float) * (3 * (size_t)np + 1)) != hipSuccess) {
@@ -1107,7 +1135,7 @@ hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, float *params, const fl
   float *G = buf, *m = buf + np, *v = buf + 2 * np, *loss = buf + 3 * np;
   hipError_t e = hipMemsetAsync(m, 0, sizeof(float) * 2 * np, s);
   for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
-    e = mlp_launch_grad(params, n_in, n_hidden, X, t, n, G, loss, s);
+    e = mlp_launch_grad(params, n_in, n_hidden, n_out, X, t, n, G, loss, s);
     if (e == hipSuccess && loss_host) e = hipMemcpyAsync(loss_host + ep, loss, sizeof(float), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = mlp_launch_adam(params, G, m, v, np, lr, ep + 1, s);
   }

@@ -76,6 +76,7 @@ class Plan:
         cD = (A.Blocks * self.n_cells)(*[a.s for a in dargs])
         th = A.Thresholds(thresholds["eps_C"], thresholds["eps_V"], thresholds["eps_D"], thresholds["eps_cs_eri"],
                           thresholds["eps_cs_mat"])
+        self.eps_mat = float(thresholds["eps_cs_mat"])
         hs = None if home_subset is None else _arr(home_subset, np.int32)
         if hs is not None and hs.shape[0] == 0:
             hs = np.zeros(1, np.int32)[:0]  # an empty subset still passes a non-NULL pointer
@@ -147,20 +148,25 @@ class Plan:
         return list(e)
 
     def item_features(self, mu, sd):
-        """Scheduler features of every item from the last build (device float32 tensor [n_items, 8])."""
+        """Scheduler features of every item from the last build (device float32 tensor
+        [n_items, ITEM_FEATURES])."""
         torch = self._torch
         mu = np.ascontiguousarray(mu, np.float32)
         sd = np.ascontiguousarray(sd, np.float32)
+        if mu.shape != (A.ITEM_FEATURES,) or sd.shape != (A.ITEM_FEATURES,):
+            raise ValueError(f"mu and sd must hold {A.ITEM_FEATURES} values")
         n = ctypes.c_int64()
-        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None))
-        X = torch.empty((n.value, 8), dtype=torch.float32, device="cuda")
+        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None, None))
+        X = torch.empty((n.value, A.ITEM_FEATURES), dtype=torch.float32, device="cuda")
         A.check(A.lib().hfx_item_features(self._h, _ptr(mu), _ptr(sd), ctypes.c_void_p(X.data_ptr())))
         return X
 
     def item_profile(self):
+        """Per-item labels of the last build: (ticks, kept-unit counters [n, 5], contribution bound)."""
         n = ctypes.c_int64()
-        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None))
+        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), None, None, None))
         cyc = np.zeros(n.value, np.int64)
         units = np.zeros((n.value, A.ITEM_UNITS), np.int64)
-        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), _ptr(cyc), _ptr(units)))
-        return cyc, units
+        contrib = np.zeros(n.value, np.float64)
+        A.check(A.lib().hfx_item_profile(self._h, ctypes.byref(n), _ptr(cyc), _ptr(units), _ptr(contrib)))
+        return cyc, units, contrib

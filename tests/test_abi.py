@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(A.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
-    assert L.hfx_abi_version() == 1
+    assert L.hfx_abi_version() == 2
 
 
 def _cstructs(w, th=None):
@@ -147,22 +147,36 @@ def test_rejects_unavailable_or_invalid_precision():
 
 def test_mlp_entry_points_validate_before_launch():
     L = A.lib()
-    assert L.hfx_mlp_n_params(8, 32) == 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
+    assert L.hfx_mlp_n_params(8, 32, 1) == 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
+    assert L.hfx_mlp_n_params(10, 32, 2) == 32 * 10 + 32 + 32 * 32 + 32 + 2 * 32 + 2
     P = ctypes.c_void_p(1)  # never dereferenced: the sizes are rejected first
-    assert L.hfx_mlp_predict(0, 32, P, P, 1, P, None) == A.HFX_ERR_ARG
-    assert L.hfx_mlp_predict(8, 65, P, P, 1, P, None) == A.HFX_ERR_ARG
-    assert L.hfx_mlp_loss_grad(8, 32, None, P, P, 1, P, P, None) == A.HFX_ERR_ARG
-    assert L.hfx_mlp_train(8, 32, P, P, P, 1, 10, ctypes.c_float(0.0), None, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_predict(0, 32, 1, P, P, 1, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_predict(8, 65, 1, P, P, 1, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_predict(8, 32, 0, P, P, 1, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_predict(8, 32, 5, P, P, 1, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_loss_grad(8, 32, 2, None, P, P, 1, P, P, None) == A.HFX_ERR_ARG
+    assert L.hfx_mlp_train(8, 32, 2, P, P, P, 1, 10, ctypes.c_float(0.0), None, None) == A.HFX_ERR_ARG
     assert L.hfx_item_features(None, None, None, None) == A.HFX_ERR_ARG
+    n = ctypes.c_int64()
+    assert L.hfx_item_profile(None, ctypes.byref(n), None, None, None) == A.HFX_ERR_ARG
 
 
 def test_scheduler_model_file_roundtrip_and_list_schedule(tmp_path):
     from paper_2009_12505_amd import sched
-    m = sched.CostModel(4, np.arange(8, dtype=np.float32), np.ones(8, np.float32),
-                        np.linspace(-1, 1, sched.n_params(4)).astype(np.float32), np.zeros(0))
+    F = sched.N_IN
+    m = sched.CostModel(4, np.arange(F, dtype=np.float32), np.ones(F, np.float32),
+                        np.linspace(-1, 1, sched.n_params(4)).astype(np.float32), np.zeros(0),
+                        np.array([1.5, -2.0], np.float32), np.array([0.5, 3.0], np.float32))
     sched.save(m, tmp_path / "m.bin")
     m2 = sched.load(tmp_path / "m.bin")
     assert m2.hidden == 4 and np.array_equal(m2.params, m.params) and np.array_equal(m2.mu, m.mu)
+    assert np.array_equal(m2.t_mu, m.t_mu) and np.array_equal(m2.t_sd, m.t_sd)
+    # the header the library reads: magic, n_in = 10, n_hidden, n_out = 2
+    raw = (tmp_path / "m.bin").read_bytes()
+    assert raw[:8] == b"HFXMLP02" and list(np.frombuffer(raw[8:20], np.int32)) == [10, 4, 2]
+    (tmp_path / "short.bin").write_bytes(raw[:-4])
+    with pytest.raises(ValueError):
+        sched.load(tmp_path / "short.bin")
     # greedy list scheduling: longest first on 2 machines is optimal here, plan order is not
     costs = np.array([1.0, 1.0, 2.0])
     assert sched.list_schedule_makespan(costs, [2, 0, 1], 2) == 2.0

@@ -1,5 +1,6 @@
 """Learned scheduler: the MLP kernels against the FP64 reference, training on the GPU,
-and what the learned order gains over the static longest-first order on uneven cells."""
+what the learned order gains over the static longest-first order on uneven cells, and how
+well the second output ranks the items' contributions against a static proxy."""
 import ctypes
 import sys
 import time
@@ -27,29 +28,30 @@ def _vp(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-@pytest.mark.parametrize("F,H,n", [(8, 32, 1000), (3, 5, 7), (8, 64, 4097), (16, 1, 1)])
-def test_mlp_forward_and_gradient_vs_fp64(F, H, n):
+@pytest.mark.parametrize("F,H,O,n", [(8, 32, 1, 1000), (3, 5, 1, 7), (8, 64, 1, 4097), (16, 1, 1, 1),
+                                     (10, 32, 2, 3000), (4, 7, 4, 33)])
+def test_mlp_forward_and_gradient_vs_fp64(F, H, O, n):
     import torch
     from paper_2009_12505_amd import lib
-    log(f"case mlp F={F} H={H} n={n}")
-    rng = np.random.default_rng(F * 1000 + H + n)
-    p = ref.init(F, H, seed=n) + rng.normal(0, 0.05, ref.n_params(F, H))
+    log(f"case mlp F={F} H={H} O={O} n={n}")
+    rng = np.random.default_rng(F * 1000 + H + n + 7 * O)
+    p = ref.init(F, H, seed=n, O=O) + rng.normal(0, 0.05, ref.n_params(F, H, O))
     X = rng.normal(size=(n, F))
-    t = rng.normal(size=n)
+    t = rng.normal(size=(n, O))
     # the reference sees the same FP32-rounded inputs
     p32, X32, t32 = p.astype(np.float32), X.astype(np.float32), t.astype(np.float32)
     P, Xd, Td = _dev(p32), _dev(X32), _dev(t32)
-    y = torch.empty(n, dtype=torch.float32, device="cuda")
-    g = torch.empty(ref.n_params(F, H), dtype=torch.float32, device="cuda")
+    y = torch.empty((n, O), dtype=torch.float32, device="cuda")
+    g = torch.empty(ref.n_params(F, H, O), dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    assert lib().hfx_mlp_n_params(F, H) == ref.n_params(F, H)
-    assert lib().hfx_mlp_predict(F, H, _vp(P), _vp(Xd), n, _vp(y), s) == 0
-    assert lib().hfx_mlp_loss_grad(F, H, _vp(P), _vp(Xd), _vp(Td), n, _vp(g), _vp(loss), s) == 0
+    assert lib().hfx_mlp_n_params(F, H, O) == ref.n_params(F, H, O)
+    assert lib().hfx_mlp_predict(F, H, O, _vp(P), _vp(Xd), n, _vp(y), s) == 0
+    assert lib().hfx_mlp_loss_grad(F, H, O, _vp(P), _vp(Xd), _vp(Td), n, _vp(g), _vp(loss), s) == 0
     torch.cuda.synchronize()
-    y_ref, _, _ = ref.forward(p32.astype(np.float64), X32, F, H)
-    L_ref, g_ref = ref.loss_grad(p32.astype(np.float64), X32, t32, F, H)
-    ey = np.max(np.abs(y.cpu().numpy() - y_ref))
+    y_ref, _, _ = ref.forward(p32.astype(np.float64), X32, F, H, O)
+    L_ref, g_ref = ref.loss_grad(p32.astype(np.float64), X32, t32, F, H, O)
+    ey = np.max(np.abs(y.cpu().numpy().reshape(y_ref.shape) - y_ref))
     eg = np.max(np.abs(g.cpu().numpy() - g_ref)) / np.max(np.abs(g_ref))
     el = abs(float(loss.cpu()[0]) - L_ref) / L_ref
     log(f"  max|dy|={ey:.2e} rel|dgrad|={eg:.2e} rel|dloss|={el:.2e}")
@@ -71,7 +73,7 @@ def test_mlp_adam_first_step_and_training():
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     lr = 1e-3
     P, Xd, Td = _dev(p0), _dev(X), _dev(t)
-    assert lib().hfx_mlp_train(F, H, _vp(P), _vp(Xd), _vp(Td), n, 1, ctypes.c_float(lr), None, s) == 0
+    assert lib().hfx_mlp_train(F, H, 1, _vp(P), _vp(Xd), _vp(Td), n, 1, ctypes.c_float(lr), None, s) == 0
     _, g_ref = ref.loss_grad(p0.astype(np.float64), X, t, F, H)
     step = P.cpu().numpy().astype(np.float64) - p0
     big = np.abs(g_ref) > 1e-4
@@ -79,7 +81,7 @@ def test_mlp_adam_first_step_and_training():
     P = _dev(p0)
     L = np.zeros(800, np.float32)
     t0 = time.time()
-    assert lib().hfx_mlp_train(F, H, _vp(P), _vp(Xd), _vp(Td), n, 800, ctypes.c_float(3e-3),
+    assert lib().hfx_mlp_train(F, H, 1, _vp(P), _vp(Xd), _vp(Td), n, 800, ctypes.c_float(3e-3),
                                L.ctypes.data_as(ctypes.c_void_p), s) == 0
     log(f"800 epochs on {n} samples: {time.time() - t0:.2f}s, loss {L[0]:.4f} -> {L[-1]:.4f}")
     assert L[-1] < 0.05 * L[0]
@@ -142,15 +144,17 @@ def test_learned_order_on_uneven_cells(tmp_path):
         res[name] = (ms, [s.cpu().numpy() for s in sig])
         if kind == SCHED_LPT:
             # ranking quality on the test homes, labels from this plan's last build
-            X, tl = sched.profile_samples(plan)
-            cyc, units = plan.item_profile()
+            X, T = sched.profile_samples(plan)
+            tl = T[:, 0]
+            cyc, units, contrib = plan.item_profile()
         log(f"order {name}: main kernel ms per build {[round(x, 1) for x in ms]}")
         del plan, sig
         torch.cuda.empty_cache()
     for c in range(len(w.cells)):
         a, b = res["lpt"][1][c], res["mlp"][1][c]
         assert np.max(np.abs(a - b)) <= 1e-12 * max(np.max(np.abs(a)), 1e-300)
-    pred = sched.predict(model, X)
+    Y = sched.predict(model, X)
+    pred = Y[:, 0]
     nfng = np.exp(X[:, 5])
     r_mlp, r_static = _spearman(pred, tl), _spearman(nfng, tl)
     # a stronger hand-made cost: the kept units of the previous build, each unit of a term
@@ -167,3 +171,13 @@ def test_learned_order_on_uneven_cells(tmp_path):
     log(f"best main-kernel ms (builds 2..4): plan {best['plan']:.1f}, lpt {best['lpt']:.1f}, mlp {best['mlp']:.1f}")
     assert r_mlp > r_static
     assert mk["mlp"] <= mk["static"] * 1.001
+    # second output: the items' contribution bounds on the held-out homes, ranked by the model
+    # and by the static proxy the plan knows before any build (closer pairs contribute more)
+    nz = contrib > 0
+    c_mlp = _spearman(Y[:, 1], contrib)
+    c_dist = _spearman(-X[:, 8], contrib)
+    c_units = _spearman(units[:, :4].sum(axis=1), contrib)
+    log(f"contribution bound: {nz.sum()} of {len(nz)} items nonzero, range {contrib[nz].min():.2e}.."
+        f"{contrib.max():.2e}; Spearman(pred, bound) = {c_mlp:.3f}, Spearman(-d_AB, bound) = {c_dist:.3f}, "
+        f"Spearman(kept units, bound) = {c_units:.3f}")
+    assert c_mlp > c_dist
