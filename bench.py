@@ -7,7 +7,8 @@ Workload: 4x4x4 conventional diamond cells (512 atoms, a = 10.26 bohr), 13 AOs /
 per atom, C within 16 bohr, screened V (omega = 0.11/bohr), all five thresholds = eps.
 Inputs are seeded synthetic blocks (hfx_synth), resident in HBM before the timed
 region.  Prints one JSON line; after an FP64 run it also times the tiered FP32/FP64 form on
-the same inputs ("mixed": build time, speedup and errors against the FP64 build).
+the same inputs ("mixed": build time, speedup and errors against the FP64 build), and the
+real-space to k-space sum of the built Sigma at 8 k-points ("fourier").
 """
 from __future__ import annotations
 
@@ -22,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TF = 78.6
 FP32_PEAK_TF = 157.3
+HBM_PEAK_GBS = 8000.0
 METRIC = "HFX build s & TFLOP/s, 512-atom Si: mixed/batched vs FP64 at 1e-8 Ha/atom"
 
 
@@ -108,6 +110,35 @@ def mixed_form(w, D, sigma64, e64, ms64, args):
     return out
 
 
+def fourier_sum(plan, sigma, reps: int):
+    """The real-space to k-space sum of the FP64 Sigma just built at the eight k-points of the
+    2x2x2 grid of the supercell's Brillouin zone (one launch): its time (HIP events on the plan
+    stream), algorithmic bytes (Sigma read once, H written once) and HBM roofline."""
+    import numpy as np
+    import torch
+    k = np.array([[a, b, c] for a in (0.0, 0.5) for b in (0.0, 0.5) for c in (0.0, 0.5)])
+    nb = plan.n_basis[0]
+    out = torch.empty((k.shape[0], nb, nb), dtype=torch.complex128, device="cuda")
+    plan.sigma_to_k(sigma, k, cell=0, out=out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        plan.sigma_to_k(sigma, k, cell=0, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    nbytes = 8.0 * plan.sizes[0] + 16.0 * k.shape[0] * nb * nb
+    gbs = nbytes / (ms / 1e3) / 1e9
+    del out
+    torch.cuda.empty_cache()
+    return {"kernel": "hfx::k_sigma_to_k", "n_k": int(k.shape[0]), "n_basis": nb, "reps": reps,
+            "ms": round(ms, 4), "algorithmic_bytes": nbytes,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +152,8 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="after an FP64 run: time this many builds of the tiered form (tau = --tau) on the "
                          "same inputs and report them against the FP64 build (0: skip)")
+    ap.add_argument("--fourier-reps", type=int, default=5,
+                    help="timed launches of the real-space to k-space sum of the built Sigma (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -214,6 +247,8 @@ def main():
         "phase_share": st["phase_share"], "plan_s": round(t_plan, 2), "gen_s": round(t_gen, 2),
         "wall_s_timed": round(t_wall, 3),
     }
+    if args.fourier_reps > 0:
+        out["fourier"] = fourier_sum(plan, sigma[0], args.fourier_reps)
     if args.precision == "fp64" and args.mixed_steps > 0:
         del plan
         out["mixed"] = mixed_form(w, D, sigma, e_x, ms_step, args)

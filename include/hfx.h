@@ -207,6 +207,24 @@ hfx_status hfx_build(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, 
  * e_x: n_cells host doubles.  Synchronises. */
 hfx_status hfx_energy(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, double *e_x);
 
+/* The step after the build in a band-structure calculation (Sec. IV,
+ * band-structure calculations, eq. Ham_rs2kspace): the matrix at k-points
+ *   H_{Ii,Jj}(k) = sum_R exp(i 2 pi k.R) Sigma_{Ii,Jj}(R)
+ * of one cell, summed over the blocks of the cell's D pattern, R the integer
+ * lattice vector of the column atom J.
+ *   cell   index of the cell in the plan
+ *   sigma  device, the cell's Sigma in hfx_sigma_layout order (e.g. from hfx_build)
+ *   n_k    number of k-points (0: nothing is done)
+ *   kfrac  host, n_k*3 doubles: k in fractional coordinates of the reciprocal
+ *          lattice (k.R = 2 pi kfrac.n_R); read during the call only
+ *   hk     device, n_k * n_basis * n_basis complex doubles (re, im interleaved),
+ *          row-major [k][row][col] with the basis ordered by atom, then AO;
+ *          every element is written.  n_basis = sum of n_ao over the cell's atoms.
+ * Stream-ordered on opt.stream; returns before completion.  Errors:
+ * HFX_ERR_ARG for a bad cell, n_k < 0, NULL arrays or non-finite k. */
+hfx_status hfx_sigma_to_k(hfx_plan *plan, int32_t cell, const double *sigma, int32_t n_k, const double *kfrac,
+                          double *hk);
+
 /* Per-item labels of the last build, for scheduler training: for each work
  * item in plan order, its main-kernel wall-clock ticks (100 MHz), five
  * counters the kernel produced (kept units of terms 1..4 after stage 3 and

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/hfx.h"
+#include "hfx_fourier.h"
 #include "hfx_internal.h"
 
 namespace hfx {
@@ -144,6 +145,10 @@ struct hfx_plan {
   bool have_profile = false;
   int mlp_f = 0, mlp_h = 0, mlp_o = 0;
   std::vector<float> item_dist;    // |r_B + R - r_A| of every item (bohr)
+  // real-space to k-space sum
+  std::vector<int32_t> ptab_off_h;        // per cell: start of its n x n pattern table
+  std::vector<long long> nbasis_cell;     // per cell: basis size
+  int32_t *bofs_dev = nullptr;            // per atom: first basis index within its cell
   float *item_dist_dev = nullptr;
   float *feat_musd = nullptr;  // normalisation for hfx_item_features
   float *mlp_params_dev = nullptr, *mlp_mu = nullptr, *mlp_sd = nullptr, *mlp_X = nullptr, *mlp_y = nullptr;
@@ -601,6 +606,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   }
   p->nD = p->dbase[n_cells];
   d_off_g.push_back(p->sbase[n_cells]);
+  p->ptab_off_h = ptab_off;
   if (p->nD > (1ll << 30)) return fail(HFX_ERR_UNSUPPORTED, "too many D blocks");
 
   // ---- per-slot scratch and LDS sizing
@@ -1087,6 +1093,46 @@ hfx_status hfx_item_features(hfx_plan *p, const float *mu, const float *sd, floa
                                 p->item_dist_dev, p->dp.cell_of, p->dp.cell_natoms, p->n_items, p->feat_musd,
                                 p->feat_musd + kItemFeatures, X, p->stream));
   HIPCHK(p, hipStreamSynchronize(p->stream));
+  return HFX_OK;
+}
+
+hfx_status hfx_sigma_to_k(hfx_plan *p, int32_t cell, const double *sigma, int32_t n_k, const double *kfrac,
+                          double *hk) {
+  if (!p) return fail(HFX_ERR_ARG, "plan is NULL");
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  if (cell < 0 || cell >= p->n_cells) return fail(HFX_ERR_ARG, "cell %d out of range (%d cells)", cell, p->n_cells);
+  if (n_k < 0) return fail(HFX_ERR_ARG, "n_k < 0");
+  if (n_k == 0) return HFX_OK;
+  if (!kfrac || !hk) return fail(HFX_ERR_ARG, "NULL k-points or output");
+  if (!sigma && p->sbase[cell + 1] > p->sbase[cell]) return fail(HFX_ERR_ARG, "sigma is NULL");
+  for (int64_t q = 0; q < 3 * (int64_t)n_k; ++q)
+    if (!std::isfinite(kfrac[q])) return fail(HFX_ERR_ARG, "k-point %lld is not finite", (long long)(q / 3));
+  hfx_status st;
+  if (!p->bofs_dev) {
+    std::vector<int32_t> b(p->nao.size());
+    p->nbasis_cell.assign(p->n_cells, 0);
+    for (int c = 0; c < p->n_cells; ++c) {
+      int32_t o = 0;
+      for (int a = p->atom_off[c]; a < p->atom_off[c + 1]; ++a) {
+        b[a] = o;
+        o += p->nao[a];
+      }
+      p->nbasis_cell[c] = o;
+    }
+    if ((st = p->upload(&p->bofs_dev, b))) return st;
+  }
+  const int n = p->atom_off[cell + 1] - p->atom_off[cell], a0 = p->atom_off[cell];
+  const long long nb = p->nbasis_cell[cell];
+  const DevPlan &P = p->dp;
+  KChunk kc;
+  for (int32_t k0 = 0; k0 < n_k; k0 += kKChunk) {
+    kc.n = std::min(kKChunk, n_k - k0);
+    for (int q = 0; q < kc.n; ++q)
+      for (int x = 0; x < 3; ++x) kc.k[q][x] = kfrac[3 * ((int64_t)k0 + q) + x];
+    HIPCHK(p, launch_sigma_to_k(sigma, P.d_off, p->sbase[cell], P.pstart + p->ptab_off_h[cell],
+                                P.pcount + p->ptab_off_h[cell], P.dsort_R, P.dsort_id, P.nao + a0, p->bofs_dev + a0, n,
+                                nb, kc, hk + (size_t)k0 * (size_t)nb * (size_t)nb * 2, p->stream));
+  }
   return HFX_OK;
 }
 

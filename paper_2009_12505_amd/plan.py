@@ -54,6 +54,8 @@ class Plan:
         self._torch = torch
         L = A.lib()
         self.n_cells = len(cells)
+        self.n_basis = [int(sum(int(cl.species_table[int(t)][0]) for t in np.asarray(cl.species).reshape(-1)))
+                        for cl in cells]
         self._keep = []
         ccells = (A.Cell * self.n_cells)()
         for i, cl in enumerate(cells):
@@ -146,6 +148,28 @@ class Plan:
         A.check(A.lib().hfx_energy(self._h, ctypes.byref(cD), ptrs, e))
         del args
         return list(e)
+
+    def sigma_to_k(self, sigma, kfrac, cell=0, out=None):
+        """H(k) = sum_R exp(i 2 pi k.R) Sigma(R) of one cell at the k-points ``kfrac`` ([n_k, 3],
+        fractional): a device complex128 tensor [n_k, n_basis, n_basis] (``out`` if given).
+        ``sigma``: the cell's device Sigma (or the list hfx_build returned).  Stream-ordered."""
+        torch = self._torch
+        if isinstance(sigma, (list, tuple)):
+            sigma = sigma[cell]
+        k = np.ascontiguousarray(np.asarray(kfrac, np.float64).reshape(-1, 3))
+        if not 0 <= cell < self.n_cells:
+            # rejected by the library (HFX_ERR_ARG) before it touches any array
+            A.check(A.lib().hfx_sigma_to_k(self._h, int(cell), None, int(k.shape[0]), _ptr(k), None))
+        nb = self.n_basis[cell]
+        if out is None:
+            out = torch.empty((k.shape[0], nb, nb), dtype=torch.complex128, device="cuda")
+        if out.dtype != torch.complex128 or tuple(out.shape) != (k.shape[0], nb, nb) or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous complex128 tensor of shape {(k.shape[0], nb, nb)}")
+        if sigma.dtype != torch.float64 or not sigma.is_cuda or sigma.numel() != self.sizes[cell]:
+            raise ValueError(f"sigma must be the cell's device float64 Sigma ({self.sizes[cell]} elements)")
+        A.check(A.lib().hfx_sigma_to_k(self._h, int(cell), ctypes.c_void_p(sigma.data_ptr()), int(k.shape[0]),
+                                       _ptr(k), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def item_features(self, mu, sd):
         """Scheduler features of every item from the last build (device float32 tensor
