@@ -8,7 +8,8 @@ per atom, C within 16 bohr, screened V (omega = 0.11/bohr), all five thresholds 
 Inputs are seeded synthetic blocks (hfx_synth), resident in HBM before the timed
 region.  Prints one JSON line; after an FP64 run it also times the tiered FP32/FP64 form on
 the same inputs ("mixed": build time, speedup and errors against the FP64 build), and the
-real-space to k-space sum of the built Sigma at 8 k-points ("fourier").
+real-space to k-space sum of the built Sigma at 8 k-points ("fourier") and the density matrix
+from eigenvectors on the primitive cell ("density").
 """
 from __future__ import annotations
 
@@ -24,6 +25,7 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TF = 78.6
 FP32_PEAK_TF = 157.3
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TF = 78.6  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
 METRIC = "HFX build s & TFLOP/s, 512-atom Si: mixed/batched vs FP64 at 1e-8 Ha/atom"
 
 
@@ -139,6 +141,46 @@ def fourier_sum(plan, sigma, reps: int):
                          "frac": round(gbs / HBM_PEAK_GBS, 4)}}
 
 
+def density_step(eps: float, reps: int):
+    """The density matrix from eigenvectors on the 2-atom primitive cell of the same crystal (the
+    step before the build, in its k-point form): an 8^3 k-grid, 4 bands (seeded eigenvectors,
+    occupation 2), D on the cell's full pattern; time (HIP events), algorithmic FLOPs (the
+    projector block of every atom pair once per k, 8 FLOP per band and element; the phase sum,
+    4 FLOP per D element and k) against the FP64 vector peak."""
+    import numpy as np
+    import torch
+    import hfx_synth as hs
+    from paper_2009_12505_amd import Plan
+    wp = hs.make_workload("cfg3prim", eps=eps)
+    plan = Plan(wp.cells, wp.C, wp.V, wp.D, wp.thresholds)
+    N, n_occ = 8, 4
+    k = np.array([[a / N, b / N, c / N] for a in range(N) for b in range(N) for c in range(N)])
+    nb = plan.n_basis[0]
+    rng = np.random.default_rng(2009)
+    ck = torch.from_numpy(rng.normal(size=(len(k), nb, n_occ)) + 1j * rng.normal(size=(len(k), nb, n_occ))).cuda()
+    occ = torch.full((len(k), n_occ), 2.0, dtype=torch.float64, device="cuda")
+    out = torch.empty(plan.sizes[0], dtype=torch.float64, device="cuda")
+    plan.density_from_k(ck, occ, k, out=out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        plan.density_from_k(ck, occ, k, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    D = wp.D[0]
+    nao = [wp.cells[0].species_table[int(t)][0] for t in wp.cells[0].species]
+    pair_elems = sum(nao[i] * nao[j] for i, j in set(zip(D.row.tolist(), D.col.tolist())))
+    flops = len(k) * (pair_elems * n_occ * 8.0 + plan.sizes[0] * 4.0)
+    tf = flops / (ms / 1e3) / 1e12
+    return {"kernel": "hfx::k_density_from_k", "workload": "2-atom primitive cell, 8^3 k-points, 4 bands",
+            "n_k": len(k), "n_basis": nb, "d_elements": plan.sizes[0], "reps": reps, "ms": round(ms, 4),
+            "flops": flops, "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": FP64_VALU_PEAK_TF,
+                                         "unit": "TFLOP/s", "frac": round(tf / FP64_VALU_PEAK_TF, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,7 +195,8 @@ def main():
                     help="after an FP64 run: time this many builds of the tiered form (tau = --tau) on the "
                          "same inputs and report them against the FP64 build (0: skip)")
     ap.add_argument("--fourier-reps", type=int, default=5,
-                    help="timed launches of the real-space to k-space sum of the built Sigma (0: skip)")
+                    help="timed launches of the real-space to k-space sum of the built Sigma and of the "
+                         "density matrix from eigenvectors (0: skip both)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -249,6 +292,7 @@ def main():
     }
     if args.fourier_reps > 0:
         out["fourier"] = fourier_sum(plan, sigma[0], args.fourier_reps)
+        out["density"] = density_step(args.eps, args.fourier_reps)
     if args.precision == "fp64" and args.mixed_steps > 0:
         del plan
         out["mixed"] = mixed_form(w, D, sigma, e_x, ms_step, args)

@@ -225,6 +225,25 @@ hfx_status hfx_energy(hfx_plan *plan, const hfx_blocks *D, double *const *sigma,
 hfx_status hfx_sigma_to_k(hfx_plan *plan, int32_t cell, const double *sigma, int32_t n_k, const double *kfrac,
                           double *hk);
 
+/* The step before the build: the real-space density matrix from Kohn-Sham
+ * eigenvectors (Sec. II, eq. DM_realspace) on the cell's D pattern,
+ *   D_{Ii,Jj}(R) = Re (1/n_k) sum_k exp(-i 2 pi k.R) sum_n f_nk c_{Ii,n}(k) conj(c_{Jj,n}(k)),
+ * R the integer lattice vector of the column atom J.  The phase is the one of
+ * the Bloch convention of hfx_sigma_to_k (eigenvectors of that H(k)), for which
+ * the two calls are each other's inverse; the real part is the whole value
+ * when the k-set is closed under k -> -k with c(-k) = conj(c(k)).
+ *   cell   index of the cell in the plan
+ *   n_k    number of k-points (>= 1); kfrac: host, n_k*3 fractional coordinates
+ *   n_occ  bands per k-point (0: D = 0)
+ *   ck     device, n_k * n_basis * n_occ complex doubles (re, im interleaved),
+ *          [k][basis][band], basis ordered by atom then AO
+ *   occ    device, n_k * n_occ doubles: the occupations f_nk
+ *   d      device, the cell's D in hfx_sigma_layout order; fully overwritten
+ * Stream-ordered on opt.stream; returns before completion.  Errors:
+ * HFX_ERR_ARG for a bad cell, n_k < 1, n_occ < 0, NULL arrays or non-finite k. */
+hfx_status hfx_density_from_k(hfx_plan *plan, int32_t cell, int32_t n_k, const double *kfrac, int32_t n_occ,
+                              const double *ck, const double *occ, double *d);
+
 /* Per-item labels of the last build, for scheduler training: for each work
  * item in plan order, its main-kernel wall-clock ticks (100 MHz), five
  * counters the kernel produced (kept units of terms 1..4 after stage 3 and

@@ -30,22 +30,31 @@ def projector(ck, occ):
     return np.einsum("kin,kn,kjn->kij", ck, occ, np.conj(ck))
 
 
+def projector_block(ci, cj, occ):
+    """Rows i of ci against rows j of cj: sum_n f_nk ci[k, i, n] conj(cj[k, j, n])."""
+    return np.einsum("kin,kn,kjn->kij", np.asarray(ci, np.complex128), np.asarray(occ, np.float64),
+                     np.conj(np.asarray(cj, np.complex128)))
+
+
 def density_from_k(cell, D, kfrac, ck, occ, pairs=None):
     """The flat D on the pattern ``D`` (offsets of ``sigma_offsets``); with ``pairs`` only the
     blocks of those (I, J) atom pairs are filled (others left at 0)."""
     kfrac = np.asarray(kfrac, np.float64).reshape(-1, 3)
-    P = projector(ck, occ)
+    ck = np.asarray(ck, np.complex128)
     bo, _ = basis_offsets(cell)
     nao = [cell.species_table[int(s)][0] for s in cell.species]
     off = sigma_offsets(cell, D)
     want = None if pairs is None else {(int(i), int(j)) for i, j in pairs}
     out = np.zeros(int(off[-1]), np.float64)
     nk = kfrac.shape[0]
+    P = {}  # the blocks of P(k) the pattern needs, one atom pair at a time
     for b in range(D.n_blocks):
         I, J = int(D.row[b]), int(D.col[b])
         if want is not None and (I, J) not in want:
             continue
+        if (I, J) not in P:
+            P[(I, J)] = projector_block(ck[:, bo[I]:bo[I] + nao[I]], ck[:, bo[J]:bo[J] + nao[J]], occ)
         phase = np.exp(-2j * np.pi * (kfrac @ np.asarray(D.R[b], np.float64)))
-        blk = (phase[:, None, None] * P[:, bo[I]:bo[I] + nao[I], bo[J]:bo[J] + nao[J]]).sum(axis=0) / nk
+        blk = (phase[:, None, None] * P[(I, J)]).sum(axis=0) / nk
         out[off[b]:off[b + 1]] = blk.real.ravel()
     return out

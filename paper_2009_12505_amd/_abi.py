@@ -19,7 +19,8 @@ SCHED_PLAN, SCHED_LPT, SCHED_MLP = 0, 1, 2
 
 EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "hfx_item_profile",
             "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",
-            "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features", "hfx_sigma_to_k"]
+            "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features", "hfx_sigma_to_k",
+            "hfx_density_from_k"]
 ITEM_UNITS = 5
 ITEM_FEATURES = 10
 ITEM_TARGETS = 2
@@ -122,6 +123,8 @@ def lib():
         L.hfx_item_features.argtypes = [P, P, P, P]
         L.hfx_sigma_to_k.restype = ctypes.c_int
         L.hfx_sigma_to_k.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P, P]
+        L.hfx_density_from_k.restype = ctypes.c_int
+        L.hfx_density_from_k.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P, P]
         if L.hfx_abi_version() != ABI_VERSION:
             raise ImportError(f"{LIB_PATH} has ABI version {L.hfx_abi_version()}, this binding expects "
                               f"{ABI_VERSION}: rebuild it with `python -m paper_2009_12505_amd.build`")

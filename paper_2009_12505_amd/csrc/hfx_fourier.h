@@ -23,4 +23,13 @@ hipError_t launch_sigma_to_k(const double *sigma, const long long *d_off, long l
                              const int32_t *nao, const int32_t *bofs, int n, long long nbasis, const KChunk &kc,
                              double *H, hipStream_t s);
 
+// D of one cell on its pattern from eigenvectors ck [k][n_basis][n_occ] (complex, interleaved)
+// and occupations occ [k][n_occ] of the kc.n k-points: D = (add ? D : 0) + scale * sum_k ...;
+// max_pcount: the largest number of pattern entries of any atom pair of the cell.
+hipError_t launch_density_from_k(const double *ck, const double *occ, int n_occ, long long nbasis,
+                                 const long long *d_off, long long sbase, const int32_t *pstart,
+                                 const int32_t *pcount, const int32_t *dsort_R, const int32_t *dsort_id,
+                                 const int32_t *nao, const int32_t *bofs, int n, int max_pcount, const KChunk &kc,
+                                 double scale, int add, double *D, hipStream_t s);
+
 }  // namespace hfx

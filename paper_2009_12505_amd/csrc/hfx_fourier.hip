@@ -95,6 +95,107 @@ __global__ __launch_bounds__(kFT) void k_sigma_to_k(const double *__restrict__ s
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// The step before the build: the real-space density matrix from Kohn-Sham eigenvectors (Sec. II,
+// eq. DM_realspace), with the phase of the Bloch convention of eq. Ham_rs2kspace (the two are
+// each other's inverse):
+//   D_{Ii,Jj}(R) = Re (1/N_k) sum_k exp(-i 2 pi k.R) P_k[Ii,Jj],
+//   P_k[Ii,Jj]   = sum_n f_nk c_{Ii,n}(k) conj(c_{Jj,n}(k)),
+// on the blocks of the cell's D pattern.  One workgroup per (atom pair I,J, chunk of kRD of the
+// pair's R entries): per k-point the rows of I and J of the eigenvector matrix are staged in LDS
+// kNC bands at a time, each thread forms one element of the pair's P_k block and adds it, with
+// the phase of each R entry of the chunk, into kRD accumulators.  P_k is never stored.
+constexpr int kRD = 16;  // R entries per workgroup
+constexpr int kNC = 32;  // bands per LDS stage
+
+__global__ __launch_bounds__(kFT) void k_density_from_k(const double2 *__restrict__ ck,
+                                                        const double *__restrict__ occ, int n_occ,
+                                                        long long nbasis, const long long *__restrict__ d_off,
+                                                        long long sbase, const int32_t *__restrict__ pstart,
+                                                        const int32_t *__restrict__ pcount,
+                                                        const int32_t *__restrict__ dsort_R,
+                                                        const int32_t *__restrict__ dsort_id,
+                                                        const int32_t *__restrict__ nao,
+                                                        const int32_t *__restrict__ bofs, int n, KChunk kc,
+                                                        double scale, int add, double *__restrict__ D) {
+  const unsigned nblk = gridDim.x, b = blockIdx.x, per = nblk / 8, rem = nblk % 8, x = b % 8;
+  const long long pair = (long long)(x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + b / 8;
+  const int r0 = blockIdx.y * kRD;
+  const int npc = pcount[pair];
+  if (r0 >= npc) return;  // uniform: this pair has fewer R entries
+  const int nr = min(kRD, npc - r0), q0 = pstart[pair] + r0;
+  const int I = (int)(pair / n), J = (int)(pair - (long long)I * n);
+  const int nI = nao[I], nJ = nao[J], ne = nI * nJ;
+  const long long rowI = bofs[I], rowJ = bofs[J];
+  __shared__ double2 sa[32][kNC], sb[32][kNC];
+  __shared__ double sf[kNC], pc[kRD], ps[kRD];
+  for (int e0 = 0; e0 < ne; e0 += kFT) {
+    const int e = e0 + (int)threadIdx.x;
+    const bool on = e < ne;
+    const int i = on ? e / nJ : 0, j = on ? e - (e / nJ) * nJ : 0;
+    double acc[kRD];
+#pragma unroll
+    for (int r = 0; r < kRD; ++r) acc[r] = 0.0;
+    for (int kq = 0; kq < kc.n; ++kq) {
+      __syncthreads();  // everyone is done with the previous k-point's phases and stages
+      if ((int)threadIdx.x < nr) {
+        const int32_t R = dsort_R[q0 + threadIdx.x];
+        const double *k = kc.k[kq];
+        double sv, cv;
+        sincospi(2.0 * (k[0] * r_of(R, 0) + k[1] * r_of(R, 1) + k[2] * r_of(R, 2)), &sv, &cv);
+        pc[threadIdx.x] = cv;
+        ps[threadIdx.x] = sv;
+      }
+      const double2 *C = ck + (long long)kq * nbasis * n_occ;
+      const double *f = occ + (long long)kq * n_occ;
+      double pre = 0.0, pim = 0.0;
+      for (int n0 = 0; n0 < n_occ; n0 += kNC) {
+        const int nn = min(kNC, n_occ - n0);
+        for (int t = threadIdx.x; t < nI * nn; t += kFT) {
+          const int rr = t / nn, c = t - rr * nn;
+          sa[rr][c] = C[(rowI + rr) * n_occ + n0 + c];
+        }
+        for (int t = threadIdx.x; t < nJ * nn; t += kFT) {
+          const int rr = t / nn, c = t - rr * nn;
+          sb[rr][c] = C[(rowJ + rr) * n_occ + n0 + c];
+        }
+        if ((int)threadIdx.x < nn) sf[threadIdx.x] = f[n0 + threadIdx.x];
+        __syncthreads();
+        if (on)
+          for (int c = 0; c < nn; ++c) {
+            const double2 a = sa[i][c], bj = sb[j][c];
+            const double w = sf[c];
+            pre = fma(w, fma(a.x, bj.x, a.y * bj.y), pre);   // Re(a conj(b))
+            pim = fma(w, fma(a.y, bj.x, -a.x * bj.y), pim);  // Im(a conj(b))
+          }
+        __syncthreads();  // the stages are rewritten by the next band chunk
+      }
+      if (n_occ <= 0) __syncthreads();  // the phases are visible before they are read
+      if (on)
+#pragma unroll
+        for (int r = 0; r < kRD; ++r)
+          if (r < nr) acc[r] = fma(pc[r], pre, fma(ps[r], pim, acc[r]));  // Re(exp(-i t) P)
+    }
+    if (on)
+      for (int r = 0; r < nr; ++r) {
+        double *dst = D + (d_off[dsort_id[q0 + r]] - sbase) + e;
+        *dst = (add ? *dst : 0.0) + scale * acc[r];
+      }
+  }
+}
+
+hipError_t launch_density_from_k(const double *ck, const double *occ, int n_occ, long long nbasis,
+                                 const long long *d_off, long long sbase, const int32_t *pstart,
+                                 const int32_t *pcount, const int32_t *dsort_R, const int32_t *dsort_id,
+                                 const int32_t *nao, const int32_t *bofs, int n, int max_pcount, const KChunk &kc,
+                                 double scale, int add, double *D, hipStream_t s) {
+  if (n <= 0 || kc.n <= 0 || max_pcount <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((long long)n * n), (unsigned)((max_pcount + kRD - 1) / kRD));
+  hipLaunchKernelGGL(k_density_from_k, grid, dim3(kFT), 0, s, reinterpret_cast<const double2 *>(ck), occ, n_occ,
+                     nbasis, d_off, sbase, pstart, pcount, dsort_R, dsort_id, nao, bofs, n, kc, scale, add, D);
+  return hipGetLastError();
+}
+
 hipError_t launch_sigma_to_k(const double *sigma, const long long *d_off, long long sbase, const int32_t *pstart,
                              const int32_t *pcount, const int32_t *dsort_R, const int32_t *dsort_id,
                              const int32_t *nao, const int32_t *bofs, int n, long long nbasis, const KChunk &kc,

@@ -147,6 +147,7 @@ struct hfx_plan {
   std::vector<float> item_dist;    // |r_B + R - r_A| of every item (bohr)
   // real-space to k-space sum
   std::vector<int32_t> ptab_off_h;        // per cell: start of its n x n pattern table
+  std::vector<int32_t> maxpc_h;           // per cell: most pattern entries of one atom pair
   std::vector<long long> nbasis_cell;     // per cell: basis size
   int32_t *bofs_dev = nullptr;            // per atom: first basis index within its cell
   float *item_dist_dev = nullptr;
@@ -603,6 +604,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       dsort_R.push_back(rp(k));
       dsort_id.push_back((int32_t)(p->dbase[c] + k));
     }
+    p->maxpc_h.push_back(n ? *std::max_element(pcount.begin() + t0, pcount.end()) : 0);
   }
   p->nD = p->dbase[n_cells];
   d_off_g.push_back(p->sbase[n_cells]);
@@ -1096,6 +1098,51 @@ hfx_status hfx_item_features(hfx_plan *p, const float *mu, const float *sd, floa
   return HFX_OK;
 }
 
+// per atom its first basis index within its cell, per cell the basis size (once per plan)
+static hfx_status ensure_basis_offsets(hfx_plan *p) {
+  if (p->bofs_dev) return HFX_OK;
+  std::vector<int32_t> b(p->nao.size());
+  p->nbasis_cell.assign(p->n_cells, 0);
+  for (int c = 0; c < p->n_cells; ++c) {
+    int32_t o = 0;
+    for (int a = p->atom_off[c]; a < p->atom_off[c + 1]; ++a) {
+      b[a] = o;
+      o += p->nao[a];
+    }
+    p->nbasis_cell[c] = o;
+  }
+  return p->upload(&p->bofs_dev, b);
+}
+
+hfx_status hfx_density_from_k(hfx_plan *p, int32_t cell, int32_t n_k, const double *kfrac, int32_t n_occ,
+                              const double *ck, const double *occ, double *d) {
+  if (!p) return fail(HFX_ERR_ARG, "plan is NULL");
+  if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
+  if (cell < 0 || cell >= p->n_cells) return fail(HFX_ERR_ARG, "cell %d out of range (%d cells)", cell, p->n_cells);
+  if (n_k < 1 || n_occ < 0) return fail(HFX_ERR_ARG, "need n_k >= 1 and n_occ >= 0");
+  if (!kfrac || (n_occ > 0 && (!ck || !occ))) return fail(HFX_ERR_ARG, "NULL k-points, eigenvectors or occupations");
+  if (!d && p->sbase[cell + 1] > p->sbase[cell]) return fail(HFX_ERR_ARG, "D is NULL");
+  for (int64_t q = 0; q < 3 * (int64_t)n_k; ++q)
+    if (!std::isfinite(kfrac[q])) return fail(HFX_ERR_ARG, "k-point %lld is not finite", (long long)(q / 3));
+  hfx_status st;
+  if ((st = ensure_basis_offsets(p))) return st;
+  const int n = p->atom_off[cell + 1] - p->atom_off[cell], a0 = p->atom_off[cell];
+  const long long nb = p->nbasis_cell[cell];
+  const DevPlan &P = p->dp;
+  KChunk kc;
+  for (int32_t k0 = 0; k0 < n_k; k0 += kKChunk) {
+    kc.n = std::min(kKChunk, n_k - k0);
+    for (int q = 0; q < kc.n; ++q)
+      for (int x = 0; x < 3; ++x) kc.k[q][x] = kfrac[3 * ((int64_t)k0 + q) + x];
+    const size_t kofs = (size_t)k0 * (size_t)n_occ;
+    HIPCHK(p, launch_density_from_k(n_occ ? ck + kofs * (size_t)nb * 2 : ck, n_occ ? occ + kofs : occ, n_occ, nb,
+                                    P.d_off, p->sbase[cell], P.pstart + p->ptab_off_h[cell],
+                                    P.pcount + p->ptab_off_h[cell], P.dsort_R, P.dsort_id, P.nao + a0,
+                                    p->bofs_dev + a0, n, p->maxpc_h[cell], kc, 1.0 / n_k, k0 > 0, d, p->stream));
+  }
+  return HFX_OK;
+}
+
 hfx_status hfx_sigma_to_k(hfx_plan *p, int32_t cell, const double *sigma, int32_t n_k, const double *kfrac,
                           double *hk) {
   if (!p) return fail(HFX_ERR_ARG, "plan is NULL");
@@ -1108,19 +1155,7 @@ hfx_status hfx_sigma_to_k(hfx_plan *p, int32_t cell, const double *sigma, int32_
   for (int64_t q = 0; q < 3 * (int64_t)n_k; ++q)
     if (!std::isfinite(kfrac[q])) return fail(HFX_ERR_ARG, "k-point %lld is not finite", (long long)(q / 3));
   hfx_status st;
-  if (!p->bofs_dev) {
-    std::vector<int32_t> b(p->nao.size());
-    p->nbasis_cell.assign(p->n_cells, 0);
-    for (int c = 0; c < p->n_cells; ++c) {
-      int32_t o = 0;
-      for (int a = p->atom_off[c]; a < p->atom_off[c + 1]; ++a) {
-        b[a] = o;
-        o += p->nao[a];
-      }
-      p->nbasis_cell[c] = o;
-    }
-    if ((st = p->upload(&p->bofs_dev, b))) return st;
-  }
+  if ((st = ensure_basis_offsets(p))) return st;
   const int n = p->atom_off[cell + 1] - p->atom_off[cell], a0 = p->atom_off[cell];
   const long long nb = p->nbasis_cell[cell];
   const DevPlan &P = p->dp;

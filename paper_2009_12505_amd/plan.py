@@ -171,6 +171,31 @@ class Plan:
                                        _ptr(k), ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def density_from_k(self, ck, occ, kfrac, cell=0, out=None):
+        """D(R) on the cell's D pattern (device float64, hfx_sigma_layout order) from eigenvectors
+        ``ck`` (device complex128 [n_k, n_basis, n_occ]) and occupations ``occ`` (device float64
+        [n_k, n_occ]) at the k-points ``kfrac`` ([n_k, 3], fractional).  Stream-ordered."""
+        torch = self._torch
+        k = np.ascontiguousarray(np.asarray(kfrac, np.float64).reshape(-1, 3))
+        if not 0 <= cell < self.n_cells:
+            A.check(A.lib().hfx_density_from_k(self._h, int(cell), int(k.shape[0]), _ptr(k), 0, None, None, None))
+        nb = self.n_basis[cell]
+        n_occ = int(ck.shape[2]) if ck.dim() == 3 else -1
+        if (ck.dtype != torch.complex128 or not ck.is_cuda or not ck.is_contiguous()
+                or tuple(ck.shape) != (k.shape[0], nb, n_occ)):
+            raise ValueError(f"ck must be a contiguous device complex128 tensor [{k.shape[0]}, {nb}, n_occ]")
+        if occ.dtype != torch.float64 or not occ.is_cuda or not occ.is_contiguous() \
+                or tuple(occ.shape) != (k.shape[0], n_occ):
+            raise ValueError(f"occ must be a contiguous device float64 tensor [{k.shape[0]}, {n_occ}]")
+        if out is None:
+            out = torch.empty(self.sizes[cell], dtype=torch.float64, device="cuda")
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() != self.sizes[cell]:
+            raise ValueError(f"out must be a device float64 tensor of {self.sizes[cell]} elements")
+        A.check(A.lib().hfx_density_from_k(self._h, int(cell), int(k.shape[0]), _ptr(k), n_occ,
+                                           ctypes.c_void_p(ck.data_ptr()), ctypes.c_void_p(occ.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def item_features(self, mu, sd):
         """Scheduler features of every item from the last build (device float32 tensor
         [n_items, ITEM_FEATURES])."""

@@ -161,6 +161,7 @@ def test_mlp_entry_points_validate_before_launch():
     assert L.hfx_item_profile(None, ctypes.byref(n), None, None, None) == A.HFX_ERR_ARG
     k = np.zeros(3)
     assert L.hfx_sigma_to_k(None, 0, P, 1, k.ctypes.data, P) == A.HFX_ERR_ARG
+    assert L.hfx_density_from_k(None, 0, 1, k.ctypes.data, 1, P, P, P) == A.HFX_ERR_ARG
 
 
 def test_scheduler_model_file_roundtrip_and_list_schedule(tmp_path):
