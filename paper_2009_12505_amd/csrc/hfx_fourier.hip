@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kFT) void k_sigma_to_k(const double *__restrict__ s
 // pair's R entries): per k-point the rows of I and J of the eigenvector matrix are staged in LDS
 // kNC bands at a time, each thread forms one element of the pair's P_k block and adds it, with
 // the phase of each R entry of the chunk, into kRD accumulators.  P_k is never stored.
-constexpr int kRD = 16;  // R entries per workgroup
+constexpr int kRD = 16;  // R entries per workgroup (4: 1.9x slower, per-k staging dominates)
 constexpr int kNC = 32;  // bands per LDS stage
 
 __global__ __launch_bounds__(kFT) void k_density_from_k(const double2 *__restrict__ ck,
