@@ -102,11 +102,14 @@ __global__ __launch_bounds__(kFT) void k_sigma_to_k(const double *__restrict__ s
 //   D_{Ii,Jj}(R) = Re (1/N_k) sum_k exp(-i 2 pi k.R) P_k[Ii,Jj],
 //   P_k[Ii,Jj]   = sum_n f_nk c_{Ii,n}(k) conj(c_{Jj,n}(k)),
 // on the blocks of the cell's D pattern.  One workgroup per (atom pair I,J, chunk of kRD of the
-// pair's R entries): per k-point the rows of I and J of the eigenvector matrix are staged in LDS
-// kNC bands at a time, each thread forms one element of the pair's P_k block and adds it, with
-// the phase of each R entry of the chunk, into kRD accumulators.  P_k is never stored.
-constexpr int kRD = 16;  // R entries per workgroup (4: 1.9x slower, per-k staging dominates)
-constexpr int kNC = 32;  // bands per LDS stage
+// pair's R entries): the rows of I and J of the eigenvector matrices are staged in LDS, up to
+// kKS k-points at a time when there are few bands (32 band-slots per stage row), else one
+// k-point and 32 bands at a time; each thread forms one element of the pair's P_k block for the
+// staged k-points and adds it, with the phase of each R entry of the chunk, into kRD
+// accumulators.  P_k is never stored.
+constexpr int kRD = 16;  // R entries per workgroup (4: 1.9x slower, the per-k staging dominates)
+constexpr int kNC = 32;  // band slots per staged row
+constexpr int kKS = 8;   // most k-points per stage
 
 __global__ __launch_bounds__(kFT) void k_density_from_k(const double2 *__restrict__ ck,
                                                         const double *__restrict__ occ, int n_occ,
@@ -127,8 +130,11 @@ __global__ __launch_bounds__(kFT) void k_density_from_k(const double2 *__restric
   const int I = (int)(pair / n), J = (int)(pair - (long long)I * n);
   const int nI = nao[I], nJ = nao[J], ne = nI * nJ;
   const long long rowI = bofs[I], rowJ = bofs[J];
-  __shared__ double2 sa[32][kNC], sb[32][kNC];
-  __shared__ double sf[kNC], pc[kRD], ps[kRD];
+  // bands per stage row and k-points per stage (nc * ksm = kNC)
+  const int nc = n_occ <= 4 ? 4 : n_occ <= 8 ? 8 : n_occ <= 16 ? 16 : kNC;
+  const int ksm = kNC / nc;
+  __shared__ double2 sa[32 * kNC], sb[32 * kNC];  // [k-point][row][band slot]
+  __shared__ double sf[kNC], pc[kKS][kRD], ps[kKS][kRD];
   for (int e0 = 0; e0 < ne; e0 += kFT) {
     const int e = e0 + (int)threadIdx.x;
     const bool on = e < ne;
@@ -136,45 +142,56 @@ __global__ __launch_bounds__(kFT) void k_density_from_k(const double2 *__restric
     double acc[kRD];
 #pragma unroll
     for (int r = 0; r < kRD; ++r) acc[r] = 0.0;
-    for (int kq = 0; kq < kc.n; ++kq) {
-      __syncthreads();  // everyone is done with the previous k-point's phases and stages
-      if ((int)threadIdx.x < nr) {
-        const int32_t R = dsort_R[q0 + threadIdx.x];
-        const double *k = kc.k[kq];
+    for (int kq0 = 0; kq0 < kc.n; kq0 += ksm) {
+      const int nks = min(ksm, kc.n - kq0);
+      __syncthreads();  // everyone is done with the previous stage's phases and rows
+      for (int t = threadIdx.x; t < nks * nr; t += kFT) {
+        const int ks = t / nr, r = t - ks * nr;
+        const int32_t R = dsort_R[q0 + r];
+        const double *k = kc.k[kq0 + ks];
         double sv, cv;
         sincospi(2.0 * (k[0] * r_of(R, 0) + k[1] * r_of(R, 1) + k[2] * r_of(R, 2)), &sv, &cv);
-        pc[threadIdx.x] = cv;
-        ps[threadIdx.x] = sv;
+        pc[ks][r] = cv;
+        ps[ks][r] = sv;
       }
-      const double2 *C = ck + (long long)kq * nbasis * n_occ;
-      const double *f = occ + (long long)kq * n_occ;
-      double pre = 0.0, pim = 0.0;
-      for (int n0 = 0; n0 < n_occ; n0 += kNC) {
-        const int nn = min(kNC, n_occ - n0);
-        for (int t = threadIdx.x; t < nI * nn; t += kFT) {
-          const int rr = t / nn, c = t - rr * nn;
-          sa[rr][c] = C[(rowI + rr) * n_occ + n0 + c];
+      double pre[kKS], pim[kKS];
+#pragma unroll
+      for (int ks = 0; ks < kKS; ++ks) pre[ks] = pim[ks] = 0.0;
+      for (int n0 = 0; n0 < n_occ; n0 += nc) {  // a single pass whenever ksm > 1
+        const int nn = min(nc, n_occ - n0);
+        for (int t = threadIdx.x; t < nks * nI * nn; t += kFT) {
+          const int ks = t / (nI * nn), u = t - ks * nI * nn, rr = u / nn, c = u - rr * nn;
+          sa[(ks * 32 + rr) * nc + c] = ck[((long long)(kq0 + ks) * nbasis + rowI + rr) * n_occ + n0 + c];
         }
-        for (int t = threadIdx.x; t < nJ * nn; t += kFT) {
-          const int rr = t / nn, c = t - rr * nn;
-          sb[rr][c] = C[(rowJ + rr) * n_occ + n0 + c];
+        for (int t = threadIdx.x; t < nks * nJ * nn; t += kFT) {
+          const int ks = t / (nJ * nn), u = t - ks * nJ * nn, rr = u / nn, c = u - rr * nn;
+          sb[(ks * 32 + rr) * nc + c] = ck[((long long)(kq0 + ks) * nbasis + rowJ + rr) * n_occ + n0 + c];
         }
-        if ((int)threadIdx.x < nn) sf[threadIdx.x] = f[n0 + threadIdx.x];
+        for (int t = threadIdx.x; t < nks * nn; t += kFT) {
+          const int ks = t / nn, c = t - ks * nn;
+          sf[ks * nc + c] = occ[(long long)(kq0 + ks) * n_occ + n0 + c];
+        }
         __syncthreads();
         if (on)
-          for (int c = 0; c < nn; ++c) {
-            const double2 a = sa[i][c], bj = sb[j][c];
-            const double w = sf[c];
-            pre = fma(w, fma(a.x, bj.x, a.y * bj.y), pre);   // Re(a conj(b))
-            pim = fma(w, fma(a.y, bj.x, -a.x * bj.y), pim);  // Im(a conj(b))
-          }
-        __syncthreads();  // the stages are rewritten by the next band chunk
+#pragma unroll
+          for (int ks = 0; ks < kKS; ++ks)
+            if (ks < nks)
+              for (int c = 0; c < nn; ++c) {
+                const double2 a = sa[(ks * 32 + i) * nc + c], bj = sb[(ks * 32 + j) * nc + c];
+                const double w = sf[ks * nc + c];
+                pre[ks] = fma(w, fma(a.x, bj.x, a.y * bj.y), pre[ks]);   // Re(a conj(b))
+                pim[ks] = fma(w, fma(a.y, bj.x, -a.x * bj.y), pim[ks]);  // Im(a conj(b))
+              }
+        __syncthreads();  // the rows are rewritten by the next band chunk
       }
       if (n_occ <= 0) __syncthreads();  // the phases are visible before they are read
       if (on)
 #pragma unroll
-        for (int r = 0; r < kRD; ++r)
-          if (r < nr) acc[r] = fma(pc[r], pre, fma(ps[r], pim, acc[r]));  // Re(exp(-i t) P)
+        for (int ks = 0; ks < kKS; ++ks)
+          if (ks < nks)
+#pragma unroll
+            for (int r = 0; r < kRD; ++r)
+              if (r < nr) acc[r] = fma(pc[ks][r], pre[ks], fma(ps[ks][r], pim[ks], acc[r]));  // Re(exp(-i t) P)
     }
     if (on)
       for (int r = 0; r < nr; ++r) {
