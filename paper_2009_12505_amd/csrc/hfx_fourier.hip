@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kFT) void k_sigma_to_k(const double *__restrict__ s
 // k-point and 32 bands at a time; each thread forms one element of the pair's P_k block for the
 // staged k-points and adds it, with the phase of each R entry of the chunk, into kRD
 // accumulators.  P_k is never stored.
-constexpr int kRD = 16;  // R entries per workgroup (4: 1.9x slower, the per-k staging dominates)
+constexpr int kRD = 8;   // R entries per workgroup (16: 7 % slower; 4 with one k-point per stage: 3x slower)
 constexpr int kNC = 32;  // band slots per staged row
 constexpr int kKS = 8;   // most k-points per stage
 
