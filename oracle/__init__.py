@@ -23,6 +23,7 @@ SRC = os.path.join(HERE, "hfxref.c")
 
 PRE, CS_ERI, CS1, CS2, CS3 = 1, 2, 4, 8, 16
 ALL_STAGES = PRE | CS_ERI | CS1 | CS2 | CS3
+DIAG_N = 14  # diag: overall max ratio, count, then per (stage, term) max ratio
 
 _lib = None
 
@@ -104,7 +105,7 @@ def run(cell, C, V, D, thresholds: dict, stages: int = ALL_STAGES, home=None, n_
     off = sigma_offsets(cell, D)
     sigma = np.zeros(int(off[-1]), np.float64)
     stats = np.zeros(16, np.int64)
-    dg = np.zeros(2, np.float64) if diag else None
+    dg = np.zeros(DIAG_N, np.float64) if diag else None
     drop = np.zeros(D.n_blocks, np.float64) if dropped else None
     nrm = np.zeros(6 * C.n_blocks + V.n_blocks + D.n_blocks, np.float64) if norms else None
     h = None if home is None else np.ascontiguousarray(home, np.int32)

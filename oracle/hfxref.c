@@ -355,9 +355,11 @@ static void ctx_free(ref_ctx *x) {
 /* stats layout (int64): [0] candidates, [1] kept_cs_eri, [2 + 4*s + t] kept at stage s+1 for
  * term t+1, [14] Y formed, [15] units formed (H computed). */
 #define ST_N 16
+#define DIAG_N 14
 
-/* diag (optional, doubles): [0] max over dropped units of max|H| / bound; [1] number of
- * dropped units examined. dropped_bound (optional, per Sigma block): sum of w * bound of
+/* diag (optional, doubles, DIAG_N entries): [0] max over dropped units of max|H| / bound;
+ * [1] number of dropped units examined; [2 + 4*(s-1) + (t-1)] the same maximum over the
+ * units of term t dropped at stage s. dropped_bound (optional, per Sigma block): sum of w * bound of
  * units dropped by stages 1-3. */
 
 static void sigma_sub(double *dst, const double *h, double w, int n) {
@@ -387,6 +389,7 @@ static int do_build(ref_ctx *x, const int32_t *home, int32_t n_home, double *sig
   memset(sigma, 0, sizeof(double) * (size_t)x->sig_off[x->D.n]);
   for (int i = 0; i < ST_N; ++i) stats[i] = 0;
   double diag_max = 0.0, diag_cnt = 0.0;
+  double diag_st[12] = {0};
   int maxP = 0, maxn = 0;
   for (int i = 0; i < x->n_atoms; ++i) {
     if (x->nabf[i] > maxP) maxP = x->nabf[i];
@@ -398,6 +401,7 @@ static int do_build(ref_ctx *x, const int32_t *home, int32_t n_home, double *sig
     int64_t ls[ST_N];
     memset(ls, 0, sizeof(ls));
     double ldmax = 0.0, ldcnt = 0.0;
+    double ldst[12] = {0};
     const size_t tsz = (size_t)maxP * maxn * maxn;
     double *Y = (double *)malloc(sizeof(double) * tsz);
     double *T = (double *)malloc(sizeof(double) * tsz);
@@ -668,6 +672,7 @@ static int do_build(ref_ctx *x, const int32_t *home, int32_t n_home, double *sig
               double m = max_abs(H, (int64_t)hr * hc);
               double r = bound > 0 ? m / bound : (m > 0 ? INFINITY : 0.0);
               if (r > ldmax) ldmax = r;
+              if (r > ldst[4 * (dropped - 1) + t]) ldst[4 * (dropped - 1) + t] = r;
               ldcnt += 1.0;
               if (dropped_bound) {
 #pragma omp atomic
@@ -685,6 +690,8 @@ static int do_build(ref_ctx *x, const int32_t *home, int32_t n_home, double *sig
     {
       for (int i = 0; i < ST_N; ++i) stats[i] += ls[i];
       if (ldmax > diag_max) diag_max = ldmax;
+      for (int i = 0; i < 12; ++i)
+        if (ldst[i] > diag_st[i]) diag_st[i] = ldst[i];
       diag_cnt += ldcnt;
     }
     free(Y);
@@ -697,6 +704,7 @@ static int do_build(ref_ctx *x, const int32_t *home, int32_t n_home, double *sig
   if (diag) {
     diag[0] = diag_max;
     diag[1] = diag_cnt;
+    for (int i = 0; i < 12; ++i) diag[2 + i] = diag_st[i];
   }
   free(items);
   free(is_home);
@@ -717,7 +725,7 @@ static void fill(ref_blocks *b, int64_t n, const int32_t *row, const int32_t *co
 /* eps: [eps_C, eps_V, eps_D, eps_cs_eri, eps_cs_matrix]; stages: REF_* bitmask.
  * sigma: output, laid out as the D pattern with offsets = running sum of
  * nao(row)*nao(col) in D-block order (sized by hfxref_sigma_size).
- * stats: int64[16]; diag: double[2] or NULL; dropped_bound: double[nD] or NULL.
+ * stats: int64[16]; diag: double[DIAG_N] or NULL; dropped_bound: double[nD] or NULL.
  * norms_out (optional, double[6*nC + nV + nD]): nA, gA, nF, gF, Q per C block,
  * then keep flags of C (as 0/1), gV, gD.  Returns 0 on success. */
 int hfxref_build(int32_t n_atoms, const int32_t *nao, const int32_t *nabf, int64_t nC, const int32_t *Crow,

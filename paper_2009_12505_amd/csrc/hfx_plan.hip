@@ -256,6 +256,21 @@ hfx_status fetch(const hfx_blocks &b, const std::vector<int64_t> &sizes, HostBlo
   return HFX_OK;
 }
 
+// a pointer the kernels dereference must be memory the GPU can reach (device, managed, or
+// pinned host memory); plain pageable host memory is rejected before any launch
+hfx_status check_gpu_ptr(const void *ptr, const char *what) {
+  hipPointerAttribute_t at;
+  const hipError_t e = hipPointerGetAttributes(&at, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HFX_ERR_ARG, "%s is not GPU-accessible memory (pass a device buffer)", what);
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged && at.type != hipMemoryTypeUnified &&
+      !(at.type == hipMemoryTypeHost && at.devicePointer))
+    return fail(HFX_ERR_ARG, "%s is not GPU-accessible memory (pass a device buffer)", what);
+  return HFX_OK;
+}
+
 hfx_status check_blocks(const hfx_blocks &b, int n_atoms, const char *what, bool need_data) {
   if (b.n_blocks < 0) return fail(HFX_ERR_ARG, "%s: negative n_blocks", what);
   if (b.n_blocks > 0 && (!b.row || !b.col || !b.R || !b.off))
@@ -891,11 +906,6 @@ static hfx_status enqueue_d(hfx_plan *p, const hfx_blocks *D) {
   return HFX_OK;
 }
 
-static hfx_status stage_d(hfx_plan *p, const hfx_blocks *D) {
-  hfx_status st = check_d(p, D);
-  return st ? st : enqueue_d(p, D);
-}
-
 // the device-side build after D is staged: D screening, Sigma clear, the persistent kernel,
 // Sigma copy-out; `eager` adds the timing events and sets the kernel's LDS attribute
 static hfx_status enqueue_core(hfx_plan *p, double *const *sigma, bool eager) {
@@ -967,6 +977,11 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     if (!sigma[c] && p->sbase[c + 1] > p->sbase[c]) return fail(HFX_ERR_ARG, "sigma[%d] is NULL", c);
   hfx_status st = check_d(p, D);
   if (st) return st;
+  for (int c = 0; c < p->n_cells; ++c) {
+    if (p->sbase[c + 1] == p->sbase[c]) continue;
+    if ((st = check_gpu_ptr(sigma[c], "sigma[c]"))) return st;
+    if (D[c].on_device && (st = check_gpu_ptr(D[c].data, "D data (on_device = 1)"))) return st;
+  }
   DevPlan &P = p->dp;
   if (p->scheduler == HFX_SCHED_MLP && p->have_profile && p->n_items > 0) {
     // learned costs from the previous build's per-item counters; longest predicted first
@@ -1038,8 +1053,14 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
 hfx_status hfx_energy(hfx_plan *p, const hfx_blocks *D, double *const *sigma, double *e_x) {
   if (!p || !sigma || !e_x) return fail(HFX_ERR_ARG, "NULL argument");
   if (p->poisoned) return fail(HFX_ERR_STATE, "plan is poisoned by an earlier HIP error");
-  hfx_status st = stage_d(p, D);
+  hfx_status st = check_d(p, D);
   if (st) return st;
+  for (int c = 0; c < p->n_cells; ++c) {
+    if (p->sbase[c + 1] == p->sbase[c]) continue;
+    if ((st = check_gpu_ptr(sigma[c], "sigma[c]"))) return st;
+    if (D[c].on_device && (st = check_gpu_ptr(D[c].data, "D data (on_device = 1)"))) return st;
+  }
+  if ((st = enqueue_d(p, D))) return st;
   std::vector<double> part(2 * p->part_blocks);
   for (int c = 0; c < p->n_cells; ++c) {
     const long long n = p->sbase[c + 1] - p->sbase[c];
@@ -1125,6 +1146,8 @@ hfx_status hfx_density_from_k(hfx_plan *p, int32_t cell, int32_t n_k, const doub
   for (int64_t q = 0; q < 3 * (int64_t)n_k; ++q)
     if (!std::isfinite(kfrac[q])) return fail(HFX_ERR_ARG, "k-point %lld is not finite", (long long)(q / 3));
   hfx_status st;
+  if (n_occ > 0 && ((st = check_gpu_ptr(ck, "ck")) || (st = check_gpu_ptr(occ, "occ")))) return st;
+  if (d && (st = check_gpu_ptr(d, "d"))) return st;
   if ((st = ensure_basis_offsets(p))) return st;
   const int n = p->atom_off[cell + 1] - p->atom_off[cell], a0 = p->atom_off[cell];
   const long long nb = p->nbasis_cell[cell];
@@ -1155,6 +1178,7 @@ hfx_status hfx_sigma_to_k(hfx_plan *p, int32_t cell, const double *sigma, int32_
   for (int64_t q = 0; q < 3 * (int64_t)n_k; ++q)
     if (!std::isfinite(kfrac[q])) return fail(HFX_ERR_ARG, "k-point %lld is not finite", (long long)(q / 3));
   hfx_status st;
+  if ((sigma && (st = check_gpu_ptr(sigma, "sigma"))) || (st = check_gpu_ptr(hk, "hk"))) return st;
   if ((st = ensure_basis_offsets(p))) return st;
   const int n = p->atom_off[cell + 1] - p->atom_off[cell], a0 = p->atom_off[cell];
   const long long nb = p->nbasis_cell[cell];

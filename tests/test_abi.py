@@ -194,3 +194,14 @@ def test_rejects_blocks_beyond_the_kernel_limits():
     keep, c, C, V, D, th = _cstructs(w)
     st, msg = _create(c, C, V, D, th)
     assert st == A.HFX_ERR_UNSUPPORTED and "n_ao" in msg
+
+
+def test_device_footprint_cap_gives_oom_before_any_allocation():
+    """max_device_bytes: plan creation fails with HFX_ERR_OOM at the first device buffer that would
+    exceed the cap (the check precedes hipMalloc, so no device is needed)."""
+    w = _tiny()
+    keep, c, C, V, D, th = _cstructs(w)
+    opt = A.Options()
+    opt.max_device_bytes = 4
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_OOM and "max_device_bytes" in msg, msg
