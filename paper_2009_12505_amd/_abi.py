@@ -89,6 +89,10 @@ def lib():
     """Load libhfx.so; raises if the HIP library has not been built."""
     global _lib
     if _lib is None:
+        # torch first: it maps its own HIP runtime (same soname), which the library must then share;
+        # loaded the other way round, the process would hold two runtimes whose device pointers and
+        # streams are not interchangeable
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_12505_amd.build`")
         L = ctypes.CDLL(LIB_PATH)

@@ -205,3 +205,14 @@ def test_device_footprint_cap_gives_oom_before_any_allocation():
     opt.max_device_bytes = 4
     st, msg = _create(c, C, V, D, th, opt)
     assert st == A.HFX_ERR_OOM and "max_device_bytes" in msg, msg
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library before torch must not map a second HIP runtime into the process (device
+    pointers and streams of one runtime are invalid in the other)."""
+    import subprocess
+    import sys
+    code = ("import paper_2009_12505_amd as p; p.lib(); import torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, text=True).strip().splitlines()[-1]
+    assert out == "1", out
