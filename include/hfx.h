@@ -285,6 +285,21 @@ hfx_status hfx_mlp_loss_grad(int32_t n_in, int32_t n_hidden, int32_t n_out, cons
 hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, int32_t n_out, float *params, const float *X, const float *t,
                          int64_t n, int32_t epochs, float lr, float *loss_host, void *stream);
 
+/* hfx_mlp_train without allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same full-batch
+ * Adam on the same loss, with the gradient, the Adam moments and the loss of the current epoch in
+ * a static device array the library holds on each GPU for the life of the process (sized for the
+ * largest model it takes: n_in <= 16, n_hidden <= 64, n_out <= 4, i.e. at most 5508 parameters,
+ * 66 KB).  The moments are cleared at the start of each call.  Stream-ordered: returns after
+ * enqueueing, without synchronising and without host copies.
+ *   params, X, t  device, as in hfx_mlp_train
+ *   loss_dev      device, epochs floats (optional): the loss before each step
+ * Every call on one GPU shares that array: calls that overlap on one GPU (two streams, two host
+ * threads) race and give undefined results; serialise them.  Errors: HFX_ERR_ARG as for
+ * hfx_mlp_train, or an argument that is not GPU-accessible memory; HFX_ERR_HIP if a launch fails. */
+hfx_status hfx_mlp_train_static(int32_t n_in, int32_t n_hidden, int32_t n_out, float *params, const float *X,
+                                const float *t, int64_t n, int32_t epochs, float lr, float *loss_dev, void *stream);
+
 /* The scheduler's 10 input features of every work item: from the last
  * build's counters log1p(kept units of terms 1..4), log1p(G formed); from the
  * plan log(|N(A)| |N(B)|), n_ao(A)/16, n_abf(A)/64, the pair distance

@@ -20,7 +20,7 @@ SCHED_PLAN, SCHED_LPT, SCHED_MLP = 0, 1, 2
 EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "hfx_item_profile",
             "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",
             "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features", "hfx_sigma_to_k",
-            "hfx_density_from_k"]
+            "hfx_density_from_k", "hfx_mlp_train_static"]
 ITEM_UNITS = 5
 ITEM_FEATURES = 10
 ITEM_TARGETS = 2
@@ -123,6 +123,9 @@ def lib():
         L.hfx_mlp_train.restype = ctypes.c_int
         L.hfx_mlp_train.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_float, P, P]
+        L.hfx_mlp_train_static.restype = ctypes.c_int
+        L.hfx_mlp_train_static.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64,
+                                           ctypes.c_int32, ctypes.c_float, P, P]
         L.hfx_item_features.restype = ctypes.c_int
         L.hfx_item_features.argtypes = [P, P, P, P]
         L.hfx_sigma_to_k.restype = ctypes.c_int

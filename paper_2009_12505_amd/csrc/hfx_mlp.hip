@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "hfx_internal.h"
 
 namespace hfx {
@@ -184,6 +186,61 @@ hipError_t mlp_launch_features(const Item *items, const int *units, const int *c
                      cell_natoms, n, mu, sd, X);
   return hipGetLastError();
 }
+// ---------------------------------------------------------------------------------------------
+// Training without allocation (hfx_mlp_train_static): the gradient, the two Adam moments and the
+// per-epoch loss live in one file-scope device array sized for the largest model the library
+// takes.  Each GPU holds its own copy until the process ends; every call on a GPU shares it.
+constexpr int kMlpScratchFloats = 3 * kMlpMaxParams + 64;
+static __device__ __align__(256) float scratch[kMlpScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` on each GPU (0: not yet looked up)
+}  // namespace
+
+// device address of this GPU's copy of `scratch`, looked up once per device with it current
+static hipError_t scratch_address(float **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<float *>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+__global__ void k_fill_zero(float *__restrict__ p, int n) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) p[q] = 0.0f;
+}
+
+int mlp_scratch_max_params() { return kMlpMaxParams; }
+
+// full-batch Adam as hfx_mlp_train, with the optimizer state in `scratch`; stream-ordered, no
+// allocation, no synchronisation; loss_dev (optional, device) receives the loss before each step
+hipError_t mlp_train_static(int F, int H, int O, float *P, const float *X, const float *T, long long n, int epochs,
+                            float lr, float *loss_dev, hipStream_t s) {
+  const int np = (int)mlp_n_params(F, H, O);
+  if (np > kMlpMaxParams) return hipErrorInvalidValue;
+  float *scr = nullptr;
+  hipError_t e = scratch_address(&scr);
+  if (e != hipSuccess) return e;
+  float *G = scr, *m = scr + kMlpMaxParams, *v = m + np, *loss = scr + 3 * kMlpMaxParams;
+  hipLaunchKernelGGL(k_fill_zero, dim3(8), dim3(256), 0, s, m, 2 * np);  // moments of the previous call
+  e = hipGetLastError();
+  for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+    e = mlp_launch_grad(P, F, H, O, X, T, n, G, loss_dev ? loss_dev + ep : loss, s);
+    if (e == hipSuccess) e = mlp_launch_adam(P, G, m, v, np, lr, ep + 1, s);
+  }
+  return e;
+}
+
 int64_t mlp_params(int F, int H, int O) { return mlp_n_params(F, H, O); }
 int mlp_max_h() { return kMlpMaxH; }
 int mlp_max_f() { return kMlpMaxF; }

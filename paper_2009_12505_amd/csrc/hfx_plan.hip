@@ -59,6 +59,9 @@ hipError_t mlp_launch_features(const Item *items, const int *units, const int *c
                                const int *nabf, const float *dist, const int *cell_of, const int *cell_natoms,
                                long long n, const float *mu, const float *sd, float *X, hipStream_t s);
 int64_t mlp_params(int F, int H, int O);
+hipError_t mlp_train_static(int F, int H, int O, float *P, const float *X, const float *T, long long n, int epochs,
+                            float lr, float *loss_dev, hipStream_t s);
+int mlp_scratch_max_params();
 int mlp_max_h();
 int mlp_max_f();
 int mlp_max_o();
@@ -1247,6 +1250,25 @@ hfx_status hfx_mlp_train(int32_t n_in, int32_t n_hidden, int32_t n_out, float *p
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(HFX_ERR_HIP, "training failed: %s", hipGetErrorString(e));
+  return HFX_OK;
+}
+
+hfx_status hfx_mlp_train_static(int32_t n_in, int32_t n_hidden, int32_t n_out, float *params, const float *X,
+                                const float *t, int64_t n, int32_t epochs, float lr, float *loss_dev, void *stream) {
+  hfx_status st = mlp_check(n_in, n_hidden, n_out, params, X, n);
+  if (st) return st;
+  if (!t || epochs < 0 || !(lr > 0)) return fail(HFX_ERR_ARG, "bad targets, epochs or learning rate");
+  if (mlp_params(n_in, n_hidden, n_out) > mlp_scratch_max_params())
+    return fail(HFX_ERR_ARG, "model has %lld parameters, the static optimizer state holds %d",
+                (long long)mlp_params(n_in, n_hidden, n_out), mlp_scratch_max_params());
+  if ((st = check_gpu_ptr(params, "params")) || (n > 0 && (st = check_gpu_ptr(X, "X"))) ||
+      (n > 0 && (st = check_gpu_ptr(t, "t"))) || (loss_dev && epochs > 0 && (st = check_gpu_ptr(loss_dev, "loss_dev"))))
+    return st;
+  const hipError_t e = mlp_train_static(n_in, n_hidden, n_out, params, X, t, n, epochs, lr, loss_dev, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HFX_ERR_HIP, "training launch failed: %s", hipGetErrorString(e));
+  }
   return HFX_OK;
 }
 
