@@ -27,6 +27,14 @@ FP32_PEAK_TF = 157.3
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TF = 78.6  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
 METRIC = "HFX build s & TFLOP/s, 512-atom Si: mixed/batched vs FP64 at 1e-8 Ha/atom"
+WORKLOADS = {
+    "cfg3": "cfg3: 512-atom Si-like supercell (4^3 conventional cells), 13 AO / 60 ABF per atom, C within 16 bohr, "
+            "HSE-screened V, all thresholds {eps:g}, precision {precision}",
+    "cfg5": "cfg5: 4096-atom Si-like supercell (8^3 conventional cells), 13 AO / 60 ABF per atom, C within 16 bohr, "
+            "HSE-screened V, all thresholds {eps:g}, precision {precision}",
+    "lr": "lr: 64-atom Si-like supercell (2^3 conventional cells), 13 AO / 60 ABF per atom, C within 12 bohr, "
+          "full-range Coulomb V to 50 bohr, all thresholds {eps:g}, precision {precision}",
+}
 
 
 def host_cpu():
@@ -228,6 +236,10 @@ def main():
     ap.add_argument("--fourier-reps", type=int, default=5,
                     help="timed launches of the real-space to k-space sum of the built Sigma and of the "
                          "density matrix from eigenvectors (0: skip both)")
+    ap.add_argument("--workload", default="cfg3", choices=["cfg3", "cfg5", "lr"],
+                    help="cfg3: the 512-atom cell (the benchmark); cfg5: the 4096-atom cell; lr: the 64-atom "
+                         "cell with the full-range Coulomb interaction (eps 1e-4)")
+    ap.add_argument("--scheduler", default="lpt", choices=["lpt", "plan", "exact", "norm", "kmeans"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -254,13 +266,18 @@ def main():
               flush=True)
         return
     t0 = time.perf_counter()
-    w = hs.make_workload("cfg3", eps=args.eps)
+    w = hs.make_workload(args.workload, eps=args.eps if args.workload != "lr" else None)
+    eps = w.thresholds["eps_cs_mat"]
     t_gen = time.perf_counter() - t0
     progress(f"inputs generated in {t_gen:.1f}s")
     t0 = time.perf_counter()
+    import paper_2009_12505_amd as hfx
     from paper_2009_12505_amd import PREC_FP32, PREC_FP64, PREC_TIERED
     prec = {"fp64": PREC_FP64, "tiered": PREC_TIERED, "fp32": PREC_FP32}[args.precision]
-    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau, use_graph=args.graph)
+    sched_kind = {"lpt": hfx.SCHED_LPT, "plan": hfx.SCHED_PLAN, "exact": hfx.SCHED_EXACT, "norm": hfx.SCHED_NORM,
+                  "kmeans": hfx.SCHED_KMEANS}[args.scheduler]
+    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau, use_graph=args.graph,
+                scheduler=sched_kind)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     progress(f"plan created in {t_plan:.1f}s")
@@ -306,15 +323,14 @@ def main():
         "build_s": round(ms_step / 1e3, 4), "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
         "dtype": {"fp64": "f64", "tiered": "f64+f32", "fp32": "f32 (f64 accumulation)"}[args.precision],
         "data": "synthetic (seeded keyed blocks, hfx_synth)",
-        "config": {"workload": "cfg3: 512-atom Si-like supercell (4^3 conventional cells), 13 AO / 60 ABF per "
-                               f"atom, C within 16 bohr, HSE-screened V, all thresholds {args.eps:g}, "
-                               f"precision {args.precision}",
-                   "eps": args.eps, "n_atoms": n_atoms, "precision": args.precision,
+        "config": {"workload": WORKLOADS[args.workload].format(eps=eps, precision=args.precision),
+                   "eps": eps, "n_atoms": n_atoms, "precision": args.precision, "scheduler": args.scheduler,
                    "tier_tau": args.tau if args.precision == "tiered" else None, "hip_graph": args.graph},
         "flops_fp32_share": round(f32 / fl_alg, 4) if fl_alg > 0 else 0.0,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": round(peak, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(args.eps) if args.precision == "fp64" else None,
+                     "traffic": measured_traffic(args.eps) if (args.precision == "fp64" and args.workload == "cfg3")
+                     else None,
                      "kernel": "hfx::k_main", "kernel_ms": round(ms_k, 3),
                      "flops_per_launch": fl_paper, "flop_count": "Algorithm 3 (same as value)",
                      "library_count": {"flops_per_launch": fl_alg, "achieved": round(achieved_lib, 4),
@@ -326,6 +342,10 @@ def main():
         "phase_share": st["phase_share"], "plan_s": round(t_plan, 2), "gen_s": round(t_gen, 2),
         "wall_s_timed": round(t_wall, 3),
     }
+    if args.workload != "cfg3":
+        args.fourier_reps = 0
+        args.mixed_steps = 0
+        args.no_cpu_baseline = True
     if args.fourier_reps > 0:
         out["fourier"] = fourier_sum(plan, sigma[0], args.fourier_reps)
         out["density"] = density_step(args.eps, args.fourier_reps)

@@ -413,15 +413,20 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
     cfg4      48 cells of 1..3 x 1..3 x 1..3 conventional cells, species 13/60 and 27/100
               drawn per site with p = 1/2, C within 12 bohr, V within 24, D within 30, eps 1e-4
     cfg5      4096 atoms (8^3 conventional cells), 13/60, eps 1e-6
+    lr        full-range Coulomb variant: 64 atoms (2^3 conventional cells), 13/60, C within 12 bohr,
+              V the unscreened (omega = 0) smeared Coulomb interaction tapered at 50 bohr, D within
+              45 bohr, eps 1e-4
+    lrprim    the 2-atom primitive cell of lr with identical keyed blocks
     tiny      user-sized cells for tests (keywords: kind, n, species_table, r_c, r_v, r_d, eps)
     """
-    idx = {"cfg1": 0, "cfg2": 1, "cfg2prim": 1, "cfg3": 2, "cfg3prim": 2, "cfg4": 3, "cfg5": 4, "tiny": 9}[name]
+    idx = {"cfg1": 0, "cfg2": 1, "cfg2prim": 1, "cfg3": 2, "cfg3prim": 2, "cfg4": 3, "cfg5": 4, "cfg5prim": 4,
+           "lr": 5, "lrprim": 5, "tiny": 9}[name]
     seed = SEED0 + idx if seed is None else seed
     if name == "cfg1":
         p = Params(r_c=12.0, r_v=12.0, r_d=12.0)
         cells = [make_cell("primitive", species_table=((13, 40),))]
         th = 0.0 if eps is None else eps
-    elif name in ("cfg2", "cfg2prim", "cfg3", "cfg3prim", "cfg5"):
+    elif name in ("cfg2", "cfg2prim", "cfg3", "cfg3prim", "cfg5", "cfg5prim"):
         p = Params(r_c=16.0, r_v=36.0, r_d=45.0)
         nabf = 40 if name.startswith("cfg2") else 60
         if name.endswith("prim"):
@@ -430,6 +435,13 @@ def make_workload(name: str, seed: int | None = None, eps: float | None = None, 
             n = {"cfg2": 2, "cfg3": 4, "cfg5": 8}[name]
             cells = [make_cell("conventional", (n, n, n), species_table=((13, nabf),))]
         th = 1e-6 if eps is None else eps
+    elif name in ("lr", "lrprim"):
+        p = Params(r_c=12.0, r_v=50.0, r_d=45.0, omega=0.0)
+        if name == "lrprim":
+            cells = [make_cell("primitive", species_table=((13, 60),))]
+        else:
+            cells = [make_cell("conventional", (2, 2, 2), species_table=((13, 60),))]
+        th = 1e-4 if eps is None else eps
     elif name == "cfg4":
         # eps 1e-4: V beyond ~20 bohr and D beyond ~28 bohr are below it before tapering
         p = Params(r_c=12.0, r_v=24.0, r_d=30.0)

@@ -117,9 +117,25 @@ typedef struct {             /* Sec. III B and III C; 0 keeps every non-zero bou
 #define HFX_SCREEN_CS3 16u   /* CS-matrix stage 3: ||C|| ||(VC)D||                         */
 #define HFX_SCREEN_ALL 31u
 
+/* Order in which the persistent kernel takes the <A,B> work items (the greedy longest-first
+ * machine scheduling of Sec. III D 1, Algorithm 6, with different cost estimates).  No order
+ * changes which units are computed, only the order of the FP64 accumulations into Sigma. */
 #define HFX_SCHED_PLAN 0    /* work items in plan order                                    */
-#define HFX_SCHED_LPT 1     /* longest-processing-time first on |N_C(A)| |N_C(B)|           */
-#define HFX_SCHED_MLP 2     /* order by the learned cost model (mlp_weights)               */
+#define HFX_SCHED_LPT 1     /* longest first on |N_C(A)| |N_C(B)| (the pre-screen proxy)    */
+#define HFX_SCHED_MLP 2     /* longest predicted first by the learned cost model (mlp_weights);
+                               the first build uses HFX_SCHED_LPT                           */
+#define HFX_SCHED_EXACT 3   /* longest first on each item's exact contraction FLOPs of the
+                               previous build (its kept units and alive G, the count of
+                               hfx_build_stats.flops_contract); the first build uses LPT    */
+#define HFX_SCHED_NORM 4    /* norm-sorted packing: largest first on the product of the block
+                               norms that enter every stage-1 bound of the item,
+                               gV_AB * max_F g(C_AF) * max_G g(C_BG), g the sqrt||X X^T||
+                               factors of Sec. III C 1 (static, known at plan time)          */
+#define HFX_SCHED_KMEANS 5  /* locality groups (the k-means distribution of Sec. III D 2,
+                               Algorithm 7, on one GPU): items clustered by k-means on the
+                               midpoints of their atom pairs into one group per XCD (8), LPT
+                               order inside a group; the workgroups of an XCD drain their own
+                               group first, then take items from the others                 */
 
 typedef struct {
   int32_t precision;          /* HFX_PREC_*                                                 */

@@ -15,7 +15,7 @@ STATUS_NAMES = ["HFX_OK", "HFX_ERR_ARG", "HFX_ERR_SHAPE", "HFX_ERR_SYMMETRY", "H
 PREC_FP64, PREC_FP32, PREC_TIERED, PREC_BF16X3 = 0, 1, 2, 3
 SCREEN_PRE, SCREEN_CS_ERI, SCREEN_CS1, SCREEN_CS2, SCREEN_CS3 = 1, 2, 4, 8, 16
 SCREEN_ALL = 31
-SCHED_PLAN, SCHED_LPT, SCHED_MLP = 0, 1, 2
+SCHED_PLAN, SCHED_LPT, SCHED_MLP, SCHED_EXACT, SCHED_NORM, SCHED_KMEANS = 0, 1, 2, 3, 4, 5
 
 EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "hfx_item_profile",
             "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",

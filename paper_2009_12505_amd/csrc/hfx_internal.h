@@ -77,12 +77,15 @@ struct DevPlan {
   int32_t max_nbr;  // max kept C blocks of any atom
   int32_t max_p, max_n;
   // counters
-  unsigned int *ticket;
+  unsigned int *ticket;           // per group: next position within the group's schedule segment
+  const int32_t *grp_start;      // n_groups + 1: schedule segments (group g: positions [start[g], start[g+1]))
+  int32_t n_groups;              // 1: one global ticket; k-means grouping: one group per XCD
   unsigned long long *counters;  // see kCnt* below
   double *flops;                 // [0] Algorithm-3 count, [1] this kernel's useful count
   long long *item_cycles;        // per item (plan order)
   int *item_units;               // per item x kItemUnits
   double *item_contrib;          // per item: summed screening bounds of its kept units
+  double *item_flops;            // per item: its contraction FLOPs (kept units and alive G)
 };
 
 enum {
@@ -100,6 +103,7 @@ enum {
 };
 
 constexpr int kItemUnits = 5;  // per item: kept units of terms 1..4, alive G
+constexpr int kMaxGroups = 16;  // schedule groups (tickets)
 constexpr int kItemFeatures = 10;  // scheduler model inputs per item
 constexpr int kItemTargets = 2;   // scheduler model outputs: log cycles, log contribution bound
 

@@ -1200,7 +1200,24 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
   const int tid = threadIdx.x;
   double *slot = P.scratch + (long long)blockIdx.x * P.slot_doubles;
   for (;;) {
-    if (tid == 0) s_item = (int)atomicAdd(P.ticket, 1u);
+    if (tid == 0) {
+      // the next item of this workgroup's group (workgroup b runs on XCD b mod 8), else of the
+      // next group that still has items: each group's segment of the schedule is drained through
+      // its own ticket; with one group this is the single global ticket
+      int found = P.n_items;
+      const int g0 = (int)(blockIdx.x % (unsigned)P.n_groups);
+      for (int q = 0; q < P.n_groups; ++q) {
+        const int g = g0 + q < P.n_groups ? g0 + q : g0 + q - P.n_groups;
+        const int n = P.grp_start[g + 1] - P.grp_start[g];
+        if (n <= 0 || __atomic_load_n(&P.ticket[g], __ATOMIC_RELAXED) >= (unsigned)n) continue;
+        const unsigned t = atomicAdd(&P.ticket[g], 1u);
+        if (t < (unsigned)n) {
+          found = P.grp_start[g] + (int)t;
+          break;
+        }
+      }
+      s_item = found;
+    }
     __syncthreads();
     const int sidx = s_item;
     if (sidx >= P.n_items) break;
@@ -1424,6 +1441,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     if (tid == 0) {
       P.item_cycles[item] = wall_clock64() - t_start;
       P.item_contrib[item] = L.contrib;
+      P.item_flops[item] = L.flops[1];
     }
     __syncthreads();
   }
@@ -1666,7 +1684,7 @@ __global__ void k_zero(double *__restrict__ p, long long n) {
 }
 
 __global__ void k_reset(unsigned int *ticket, unsigned long long *counters, double *flops) {
-  if (threadIdx.x == 0) *ticket = 0;
+  if (threadIdx.x < kMaxGroups) ticket[threadIdx.x] = 0;
   if (threadIdx.x < kCntN) counters[threadIdx.x] = 0;
   if (threadIdx.x < 2) flops[threadIdx.x] = 0.0;
 }

@@ -104,6 +104,60 @@ bool r_ok(const int32_t *R) {
   return true;
 }
 
+// Lloyd's k-means on points x (n x 3) into k groups: seeds by farthest-point selection from the
+// first point (deterministic), then `iters` rounds of assignment to the nearest centre and
+// re-centring.  Returns the group of every point.
+std::vector<int> kmeans_groups(const std::vector<double> &x, int k, int iters) {
+  const size_t n = x.size() / 3;
+  std::vector<int> g(n, 0);
+  if (n == 0 || k <= 1) return g;
+  k = (int)std::min<size_t>((size_t)k, n);
+  std::vector<double> c(3 * (size_t)k), dmin(n, 1e300);
+  auto d2 = [&](size_t i, const double *y) {
+    const double a = x[3 * i] - y[0], b = x[3 * i + 1] - y[1], e = x[3 * i + 2] - y[2];
+    return a * a + b * b + e * e;
+  };
+  size_t pick = 0;
+  for (int q = 0; q < k; ++q) {
+    for (int t = 0; t < 3; ++t) c[3 * q + t] = x[3 * pick + t];
+    size_t far = 0;
+    for (size_t i = 0; i < n; ++i) {
+      dmin[i] = std::min(dmin[i], d2(i, &c[3 * q]));
+      if (dmin[i] > dmin[far]) far = i;
+    }
+    pick = far;
+  }
+  std::vector<double> sum(3 * (size_t)k);
+  std::vector<size_t> cnt(k);
+  for (int it = 0; it < iters; ++it) {
+    bool moved = false;
+    for (size_t i = 0; i < n; ++i) {
+      int best = 0;
+      double bd = d2(i, &c[0]);
+      for (int q = 1; q < k; ++q) {
+        const double d = d2(i, &c[3 * q]);
+        if (d < bd) {
+          bd = d;
+          best = q;
+        }
+      }
+      moved |= best != g[i];
+      g[i] = best;
+    }
+    std::fill(sum.begin(), sum.end(), 0.0);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (size_t i = 0; i < n; ++i) {
+      for (int t = 0; t < 3; ++t) sum[3 * g[i] + t] += x[3 * i + t];
+      ++cnt[g[i]];
+    }
+    for (int q = 0; q < k; ++q)
+      if (cnt[q])
+        for (int t = 0; t < 3; ++t) c[3 * q + t] = sum[3 * q + t] / (double)cnt[q];
+    if (!moved && it > 0) break;
+  }
+  return g;
+}
+
 }  // namespace
 
 struct hfx_plan {
@@ -157,6 +211,7 @@ struct hfx_plan {
   float *feat_musd = nullptr;  // normalisation for hfx_item_features
   float *mlp_params_dev = nullptr, *mlp_mu = nullptr, *mlp_sd = nullptr, *mlp_X = nullptr, *mlp_y = nullptr;
   std::vector<int32_t> lpt_order;
+  int n_groups = 1;
   int part_blocks = 1024;
   double *staging = nullptr;  // pinned host staging for D
   size_t staging_n = 0;
@@ -290,6 +345,47 @@ hfx_status check_blocks(const hfx_blocks &b, int n_atoms, const char *what, bool
 
 }  // namespace
 
+// Copy blocks (source, length) into dst at the packed offsets off[k] (increasing; the gaps are
+// zero padding) through a pinned staging buffer of at most 256 MiB.
+static hfx_status upload_packed(hfx_plan *p, double *dst, const std::vector<std::pair<const double *, int64_t>> &jobs,
+                                const std::vector<long long> &off) {
+  if (jobs.empty()) return HFX_OK;
+  const int64_t total = off.back() + (jobs.back().second + 31) / 32 * 32;
+  const int64_t cap = std::min<int64_t>(total, (int64_t)1 << 25);  // doubles
+  double *pin = nullptr;
+  if (hipHostMalloc((void **)&pin, (size_t)cap * sizeof(double)) != hipSuccess) return p->hip_fail("hipHostMalloc");
+  hfx_status st = HFX_OK;
+  int64_t d0 = 0, fill = 0;  // chunk start in dst, doubles staged
+  auto flush = [&]() {
+    if (fill > 0 && hipMemcpy(dst + d0, pin, (size_t)fill * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return false;
+    return true;
+  };
+  for (size_t k = 0; k < jobs.size() && st == HFX_OK; ++k) {
+    const int64_t n = jobs[k].second, padded = (n + 31) / 32 * 32;
+    if (padded > cap) {
+      st = fail(HFX_ERR_UNSUPPORTED, "a block of %lld elements exceeds the upload stage", (long long)n);
+      break;
+    }
+    if (off[k] + padded - d0 > cap) {
+      if (!flush()) {
+        st = p->hip_fail("hipMemcpy");
+        break;
+      }
+      d0 = off[k];
+      fill = 0;
+    }
+    double *q = pin + (off[k] - d0);
+    if (off[k] - d0 > fill) std::memset(pin + fill, 0, (size_t)(off[k] - d0 - fill) * sizeof(double));
+    std::memcpy(q, jobs[k].first, (size_t)n * sizeof(double));
+    std::memset(q + n, 0, (size_t)(padded - n) * sizeof(double));
+    fill = off[k] - d0 + padded;
+  }
+  if (st == HFX_OK && !flush()) st = p->hip_fail("hipMemcpy");
+  (void)hipHostFree(pin);
+  return st;
+}
+
 extern "C" {
 
 int32_t hfx_abi_version(void) { return HFX_ABI_VERSION; }
@@ -315,7 +411,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     return fail(HFX_ERR_ARG, "unknown precision %d", o.precision);
   if (o.precision == HFX_PREC_TIERED && !(o.tier_tau >= 0 && std::isfinite(o.tier_tau)))
     return fail(HFX_ERR_ARG, "tier_tau must be finite and >= 0");
-  if (o.scheduler < HFX_SCHED_PLAN || o.scheduler > HFX_SCHED_MLP)
+  if (o.scheduler < HFX_SCHED_PLAN || o.scheduler > HFX_SCHED_KMEANS)
     return fail(HFX_ERR_ARG, "unknown scheduler %d", o.scheduler);
   if (o.scheduler == HFX_SCHED_MLP && !o.mlp_weights)
     return fail(HFX_ERR_ARG, "HFX_SCHED_MLP needs mlp_weights");
@@ -477,16 +573,11 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   if (max_nbr > main_maxnb())
     return fail(HFX_ERR_UNSUPPORTED, "an atom has %d kept C blocks (limit %d)", max_nbr, main_maxnb());
   const int nC = (int)c_row.size();
-  std::vector<double> cstage((size_t)cdoubles, 0.0);
-  {
-    int kk = 0;
-    for (int a = 0; a < NA; ++a)
-      for (const KC &kc : crow[a]) {
-        std::memcpy(cstage.data() + c_off[kk], hC[kc.cell].data + C[kc.cell].off[kc.k],
-                    csz[kc.cell][kc.k] * sizeof(double));
-        ++kk;
-      }
-  }
+  // kept C blocks in device order: (source, length); the device copy is packed by c_off
+  std::vector<std::pair<const double *, int64_t>> cjobs;
+  cjobs.reserve(nC);
+  for (int a = 0; a < NA; ++a)
+    for (const KC &kc : crow[a]) cjobs.emplace_back(hC[kc.cell].data + C[kc.cell].off[kc.k], csz[kc.cell][kc.k]);
 
   // ---- kept V
   std::vector<int32_t> v_row, v_col, v_Rp;
@@ -506,12 +597,10 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     }
   }
   const int nV = (int)v_row.size();
-  std::vector<double> vstage((size_t)vdoubles, 0.0);
-  for (int c = 0, kk = 0; c < n_cells; ++c)
-    for (int k : vkept[c]) {
-      std::memcpy(vstage.data() + v_off[kk], hV[c].data + V[c].off[k], vsz[c][k] * sizeof(double));
-      ++kk;
-    }
+  std::vector<std::pair<const double *, int64_t>> vjobs;
+  vjobs.reserve(nV);
+  for (int c = 0; c < n_cells; ++c)
+    for (int k : vkept[c]) vjobs.emplace_back(hV[c].data + V[c].off[k], vsz[c][k]);
 
   // ---- CS-ERI sources per kept C block: C(F,A,-R), V(A,A,0), V(A,F,R), V(F,A,-R), V(F,F,0)
   std::vector<int32_t> qsrc((size_t)nC * 5, -1);
@@ -544,7 +633,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   }
 
   // ---- items: kept V blocks (A,B,R) with A a home atom; LPT cost = |N(A)| |N(B)|
-  std::vector<double> cost;
+  std::vector<double> cost, mid;
   for (int vb = 0; vb < nV; ++vb) {
     const int A = v_row[vb], B = v_col[vb];
     if (!is_home[A]) continue;
@@ -563,13 +652,30 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
         d2 += dx * dx;
       }
       p->item_dist.push_back((float)std::sqrt(d2));
+      // midpoint of the pair (cells kept apart by a large offset so that no group spans two)
+      for (int x = 0; x < 3; ++x) {
+        const double rb = cl.pos[3 * lb + x] + r_of(rp, 0) * cl.lattice[x] + r_of(rp, 1) * cl.lattice[3 + x] +
+                          r_of(rp, 2) * cl.lattice[6 + x];
+        mid.push_back(0.5 * (cl.pos[3 * la + x] + rb) + (x == 0 ? 1e5 * p->cell_of[A] : 0.0));
+      }
     }
   }
   p->n_items = (int64_t)p->items.size();
   p->order.resize(p->n_items);
   std::iota(p->order.begin(), p->order.end(), 0);
-  if (p->scheduler != HFX_SCHED_PLAN)  // the learned order starts from LPT until a build has run
+  if (p->scheduler != HFX_SCHED_PLAN)  // learned and exact orders start from LPT until a build has run
     std::stable_sort(p->order.begin(), p->order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<int32_t> grp_start{0, (int32_t)p->n_items};
+  if (p->scheduler == HFX_SCHED_KMEANS && p->n_items > 0) {
+    // one group per XCD; inside a group the LPT order above
+    const int k = 8;
+    const std::vector<int> g = kmeans_groups(mid, k, 30);
+    std::stable_sort(p->order.begin(), p->order.end(), [&](int x, int y) { return g[x] < g[y]; });
+    grp_start.assign(k + 1, 0);
+    for (int64_t i = 0; i < p->n_items; ++i) ++grp_start[g[i] + 1];
+    for (int q = 0; q < k; ++q) grp_start[q + 1] += grp_start[q];
+  }
+  p->n_groups = (int)grp_start.size() - 1;
 
   // ---- D pattern: compact offsets, sorted lookup, pair tables
   p->d_row.resize(n_cells);
@@ -694,20 +800,21 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   uint8_t *d_keepD = nullptr;
   Item *d_items = nullptr;
   unsigned int *d_ticket = nullptr;
+  int32_t *d_grp = nullptr;
   unsigned long long *d_cnt = nullptr;
   double *d_flops = nullptr;
   long long *d_icyc = nullptr;
   int *d_iunits = nullptr;
-  double *d_icontrib = nullptr;
+  double *d_icontrib = nullptr, *d_iflops = nullptr;
   std::vector<int32_t> ord32(p->order.begin(), p->order.end());
   if ((st = p->upload(&d_nao, p->nao)) || (st = p->upload(&d_nabf, p->nabf)) ||
       (st = p->upload(&d_cellof, p->cell_of)) || (st = p->upload(&d_localof, p->local_of)) ||
       (st = p->upload(&d_cstart, c_start)) || (st = p->upload(&d_ccol, c_col)) || (st = p->upload(&d_crow, c_row)) ||
-      (st = p->upload(&d_cR, c_Rp)) || (st = p->upload(&d_coff, c_off)) || (st = p->upload(&d_C, cstage)) ||
-      (st = p->dalloc(&d_CT, cstage.size())) ||
-      (p->tier && ((st = p->dalloc(&d_C32, cstage.size())) || (st = p->dalloc(&d_CT32, cstage.size())))) ||
+      (st = p->upload(&d_cR, c_Rp)) || (st = p->upload(&d_coff, c_off)) || (st = p->dalloc(&d_C, (size_t)cdoubles)) ||
+      (st = p->dalloc(&d_CT, (size_t)cdoubles)) ||
+      (p->tier && ((st = p->dalloc(&d_C32, (size_t)cdoubles)) || (st = p->dalloc(&d_CT32, (size_t)cdoubles)))) ||
       (st = p->upload(&d_vrow, v_row)) || (st = p->upload(&d_vcol, v_col)) || (st = p->upload(&d_voff, v_off)) ||
-      (st = p->upload(&d_V, vstage)) || (st = p->upload(&d_qsrc, qsrc)) || (st = p->dalloc(&d_cn, nC)) ||
+      (st = p->dalloc(&d_V, (size_t)vdoubles)) || (st = p->upload(&d_qsrc, qsrc)) || (st = p->dalloc(&d_cn, nC)) ||
       (st = p->dalloc(&d_gV, nV)) || (st = p->upload(&d_ptoff, ptab_off)) || (st = p->upload(&d_pstart, pstart)) ||
       (st = p->upload(&d_pcount, pcount)) || (st = p->upload(&d_dsR, dsort_R)) ||
       (st = p->upload(&d_dsid, dsort_id)) || (st = p->upload(&d_cellnat, p->cell_natoms)) ||
@@ -715,15 +822,14 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
       (st = p->upload(&d_dcol, p->d_col_g)) || (st = p->dalloc(&d_D, (size_t)p->sbase[n_cells])) ||
       (st = p->dalloc(&d_S, (size_t)p->sbase[n_cells])) || (st = p->dalloc(&d_gD, (size_t)p->nD)) ||
       (st = p->dalloc(&d_keepD, (size_t)p->nD)) || (st = p->upload(&d_items, p->items)) ||
-      (st = p->upload(&d_order, ord32)) || (st = p->dalloc(&d_ticket, 1)) || (st = p->dalloc(&d_cnt, kCntN)) ||
+      (st = p->upload(&d_order, ord32)) || (st = p->dalloc(&d_ticket, kMaxGroups)) || (st = p->upload(&d_grp, grp_start)) || (st = p->dalloc(&d_cnt, kCntN)) ||
       (st = p->dalloc(&d_flops, 2)) || (st = p->dalloc(&d_icyc, (size_t)p->n_items)) || (st = p->dalloc(&d_iunits, (size_t)p->n_items * kItemUnits)) ||
-      (st = p->dalloc(&d_icontrib, (size_t)p->n_items)) || (st = p->upload(&p->item_dist_dev, p->item_dist)) ||
+      (st = p->dalloc(&d_icontrib, (size_t)p->n_items)) || (st = p->dalloc(&d_iflops, (size_t)p->n_items)) || (st = p->upload(&p->item_dist_dev, p->item_dist)) ||
       (st = p->dalloc(&d_scr, (size_t)p->n_slots * slot)) || (st = p->dalloc(&p->part, 2 * p->part_blocks)))
     return st;
-  cstage.clear();
-  cstage.shrink_to_fit();
-  vstage.clear();
-  vstage.shrink_to_fit();
+  // block data through a pinned staging buffer, chunk by chunk: the host never holds a packed
+  // copy of C or V (blocks that alias in the caller's arrays are read in place)
+  if ((st = upload_packed(p, d_C, cjobs, c_off)) || (st = upload_packed(p, d_V, vjobs, v_off))) return st;
   {
     std::vector<long long> db(p->dbase.begin(), p->dbase.end());
     if ((st = p->upload(&p->dbase_dev, db)) || (st = p->dalloc(&p->gDmax_dev, n_cells))) return st;
@@ -779,17 +885,21 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   P.max_p = max_p;
   P.max_n = max_n;
   P.ticket = d_ticket;
+  P.grp_start = d_grp;
+  P.n_groups = p->n_groups;
   P.counters = d_cnt;
   P.flops = d_flops;
   P.item_cycles = d_icyc;
   P.item_units = d_iunits;
   P.item_contrib = d_icontrib;
+  P.item_flops = d_iflops;
 
   {
     const void *must[] = {P.nao, P.nabf, P.cell_of, P.local_of, P.Cbuf, P.CTbuf, P.c_off, P.c_col, P.c_R, P.c_norm,
                           P.c_start, P.Vbuf, P.v_off, P.gV, P.ptab_off, P.pstart, P.pcount, P.dsort_R, P.dsort_id,
                           P.cell_natoms, P.d_off, P.Dbuf, P.gD, P.keepD, P.gDmax, P.Sbuf, P.items, P.order,
                           P.scratch, P.ticket, P.counters, P.flops, P.item_cycles, P.item_units, P.item_contrib,
+                          P.item_flops,
                           p->item_dist_dev, p->part,
                           p->d_row_dev, p->d_col_dev, p->dbase_dev};
     for (const void *q : must)
@@ -834,6 +944,26 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   }
   HIPCHK(p, launch_cq(d_C, d_coff, d_crow, d_ccol, d_V, d_voff, d_qsrc, d_nao, d_nabf, nC, d_cn, p->stream));
   HIPCHK(p, launch_vnorm(d_V, d_voff, d_vrow, d_vcol, d_nabf, nV, d_gV, p->stream));
+  if (p->scheduler == HFX_SCHED_NORM && p->n_items > 0) {
+    // norm-sorted packing: gV_AB * max_F g(C_AF) * max_G g(C_BG), largest first
+    std::vector<double> gv(nV);
+    std::vector<CNorm> cn(nC);
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    if (nV) HIPCHK(p, hipMemcpy(gv.data(), d_gV, gv.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (nC) HIPCHK(p, hipMemcpy(cn.data(), d_cn, cn.size() * sizeof(CNorm), hipMemcpyDeviceToHost));
+    std::vector<double> gmax(NA, 0.0), key(p->n_items);
+    for (int a = 0; a < NA; ++a)
+      for (int q = c_start[a]; q < c_start[a + 1]; ++q) gmax[a] = std::max({gmax[a], cn[q].gA, cn[q].gF});
+    for (int64_t i = 0; i < p->n_items; ++i) {
+      const Item &it = p->items[i];
+      key[i] = gv[it.vid] * gmax[it.A] * gmax[it.B];
+    }
+    std::vector<int32_t> ord(p->n_items);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] > key[y]; });
+    p->order = ord;
+    HIPCHK(p, hipMemcpy(d_order, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   HIPCHK(p, hipEventCreate(&p->ev0));
   HIPCHK(p, hipEventCreate(&p->ev1));
   HIPCHK(p, hipEventCreate(&p->ev2));
@@ -1003,6 +1133,18 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     for (int64_t i = 0; i < p->n_items; ++i) bucket[i] = (int32_t)std::floor(pred[i] * 10.0f);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bucket[x] > bucket[y]; });
+    HIPCHK(p, hipMemcpyAsync(const_cast<int32_t *>(P.order), ord.data(), ord.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+  }
+  if (p->scheduler == HFX_SCHED_EXACT && p->have_profile && p->n_items > 0) {
+    // exact costs: the contraction FLOPs each item did in the previous build, longest first
+    std::vector<double> fl(p->n_items);
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    HIPCHK(p, hipMemcpy(fl.data(), P.item_flops, fl.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<int32_t> ord(p->n_items);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return fl[x] > fl[y]; });
     HIPCHK(p, hipMemcpyAsync(const_cast<int32_t *>(P.order), ord.data(), ord.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, p->stream));
     HIPCHK(p, hipStreamSynchronize(p->stream));

@@ -140,6 +140,28 @@ def load(path) -> CostModel:
                      v[o:o + N_OUT].copy(), v[o + N_OUT:].copy())
 
 
+def choose_by_build_time(make_plan, D, kinds, reps: int = 3):
+    """The fallback rule: build with each scheduler kind (one warm-up build, whose order is the
+    static one for the kinds that learn from a previous build, then ``reps`` timed builds) and
+    keep the kind with the smallest median main-kernel time.  ``make_plan(kind)`` returns a Plan.
+    Returns (best kind, {kind: median ms}, {kind: [ms of the timed builds]})."""
+    import torch
+    med, runs = {}, {}
+    for kind in kinds:
+        plan = make_plan(kind)
+        plan.build(D, stats=True)
+        ms = []
+        for _ in range(reps):
+            plan.build(D, stats=True)
+            ms.append(plan.last_stats["ms_main"])
+        runs[kind] = ms
+        med[kind] = float(np.median(ms))
+        del plan
+        torch.cuda.empty_cache()
+    best = min(med, key=med.get)
+    return best, med, runs
+
+
 def list_schedule_makespan(costs, order, n_machines: int) -> float:
     """Makespan of greedy list scheduling: items taken in `order`, each by the machine that
     frees first (what the atomic ticket of the persistent kernel does)."""
