@@ -27,6 +27,8 @@ FP32_PEAK_TF = 157.3
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TF = 78.6  # 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 (FMA) x 2.4 GHz
 METRIC = "HFX build s & TFLOP/s, 512-atom Si: mixed/batched vs FP64 at 1e-8 Ha/atom"
+BF16X3_PEAK_TF = 2516.6 / 3.0  # useful FP32-equivalent rate of split-BF16x3 products
+TUNING_DB = os.path.join(ROOT, "paper_2009_12505_amd", "tuning", "mi355x.txt")
 WORKLOADS = {
     "cfg3": "cfg3: 512-atom Si-like supercell (4^3 conventional cells), 13 AO / 60 ABF per atom, C within 16 bohr, "
             "HSE-screened V, all thresholds {eps:g}, precision {precision}",
@@ -117,13 +119,23 @@ def measured_traffic(eps: float):
         return None
 
 
-def mixed_form(w, D, sigma64, e64, ms64, args):
-    """The tiered FP32/FP64 form on the same inputs: its build time and its Sigma / E_x against
-    the FP64 build just timed."""
+def mixed_form(w, D, sigma64, e64, ms64, args, precision="tiered"):
+    """A tiered form (FP64/FP32, or FP64/FP32/split-BF16x3) on the same inputs: its build time and
+    its Sigma / E_x against the FP64 build just timed.  Tier bounds and tiles from the tuning file
+    when it holds this key, else --tau / --tau-bf."""
     import torch
-    from paper_2009_12505_amd import PREC_TIERED, Plan
+    from paper_2009_12505_amd import PREC_BF16X3, PREC_TIERED, Plan
     torch.cuda.empty_cache()
-    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=PREC_TIERED, tier_tau=args.tau)
+    prec = {"tiered": PREC_TIERED, "bf16x3": PREC_BF16X3}[precision]
+    kw = dict(precision=prec, tier_tau=args.tau, tier_tau_bf=args.tau_bf)
+    if args.tuning_db:
+        try:
+            plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, tuning_db=args.tuning_db,
+                        **dict(kw, tier_tau=-1.0, tier_tau_bf=-1.0 if prec == PREC_BF16X3 else 0.0))
+        except Exception:  # no entry for this key: the command-line bounds
+            plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, tuning_db=args.tuning_db, **kw)
+    else:
+        plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, **kw)
     sigma = plan.alloc_sigma()
     plan.build(D, sigma, stats=True)
     progress(f"tiered warmup build: {plan.last_stats['ms_main']:.1f} ms")
@@ -142,9 +154,11 @@ def mixed_form(w, D, sigma64, e64, ms64, args):
     dsig = max(float((a - b).abs().max()) for a, b in zip(sigma, sigma64))
     n_atoms = w.cells[0].n_atoms
     fl = st["flops_contract"]
-    out = {"precision": "tiered", "tier_tau": args.tau, "steps": args.mixed_steps, "build_s": round(ms / 1e3, 4),
+    out = {"precision": precision, "tier_tau": st["tier_tau"], "tier_tau_bf": st["tier_tau_bf"],
+           "tile_r": st["tile_r"], "steps": args.mixed_steps, "build_s": round(ms / 1e3, 4),
            "speedup_vs_fp64": round(ms64 / ms, 4),
            "flops_fp32_share": round(st["flops_tier"][1] / fl, 4) if fl > 0 else 0.0,
+           "flops_bf16x3_share": round(st["flops_tier"][2] / fl, 4) if fl > 0 else 0.0,
            "max_abs_dsigma_vs_fp64": dsig, "de_x_per_atom_vs_fp64": abs(e - e64) / n_atoms}
     del plan, sigma
     torch.cuda.empty_cache()
@@ -220,14 +234,44 @@ def density_step(eps: float, reps: int):
                                          "unit": "TFLOP/s", "frac": round(tf / FP64_VALU_PEAK_TF, 4)}}
 
 
+def run_tuner(w, args):
+    """Autotune the workload on a seeded subset of home atoms for the three precision forms and
+    append the choices to the tuning file."""
+    import numpy as np
+    from paper_2009_12505_amd import PREC_BF16X3, PREC_FP64, PREC_TIERED, tune
+    db = args.tuning_db or TUNING_DB
+    os.makedirs(os.path.dirname(db), exist_ok=True)
+    rng = np.random.default_rng(2009)
+    home = sorted(rng.choice(w.cells[0].n_atoms, size=min(args.tune_homes, w.cells[0].n_atoms),
+                             replace=False).tolist())
+    out = {}
+    for name, prec in (("fp64", PREC_FP64), ("tiered", PREC_TIERED), ("bf16x3", PREC_BF16X3)):
+        key, best, cands = tune.tune(w.cells, w.C, w.V, w.D, w.D, w.thresholds, prec, home, db_path=db,
+                                     log=progress)
+        out[name] = {"key": key, "tile_r": best.tile_r, "tier_tau": best.tier_tau, "tier_tau_bf": best.tier_tau_bf,
+                     "ms_subset": round(best.ms, 2),
+                     "candidates": [dict(tile_r=c.tile_r, tier_tau=c.tier_tau, tier_tau_bf=c.tier_tau_bf,
+                                         ms=round(c.ms, 2), max_dsigma=c.max_dsigma, de_x_atom=c.de_x_atom,
+                                         admitted=c.admitted) for c in cands]}
+    print(json.dumps({"tuning_db": os.path.relpath(db, ROOT), "home_atoms": len(home), "workload": args.workload,
+                      "eps": w.thresholds["eps_cs_mat"], "choices": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--eps", type=float, default=1e-6)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "tiered", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "tiered", "fp32", "bf16x3"])
     ap.add_argument("--tau", type=float, default=1e-3, help="tier bound of the tiered form")
+    ap.add_argument("--tau-bf", type=float, default=1e-5, help="split-BF16x3 tier bound (bf16x3 form)")
+    ap.add_argument("--tuning-db", default=TUNING_DB if os.path.exists(TUNING_DB) else None,
+                    help="tuning file of tile widths and tier bounds (default: the committed one)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner on a subset of home atoms of the workload (fp64, tiered, bf16x3) "
+                         "and append its choices to --tuning-db (default: the committed file), then exit")
+    ap.add_argument("--tune-homes", type=int, default=32, help="home atoms of the tuning subset")
     ap.add_argument("--graph", action="store_true",
                     help="replay the build as one captured HIP graph (kernel time = whole graph)")
     ap.add_argument("--mixed-steps", type=int, default=1,
@@ -268,16 +312,19 @@ def main():
     t0 = time.perf_counter()
     w = hs.make_workload(args.workload, eps=args.eps if args.workload != "lr" else None)
     eps = w.thresholds["eps_cs_mat"]
+    if args.tune:
+        run_tuner(w, args)
+        return
     t_gen = time.perf_counter() - t0
     progress(f"inputs generated in {t_gen:.1f}s")
     t0 = time.perf_counter()
     import paper_2009_12505_amd as hfx
     from paper_2009_12505_amd import PREC_FP32, PREC_FP64, PREC_TIERED
-    prec = {"fp64": PREC_FP64, "tiered": PREC_TIERED, "fp32": PREC_FP32}[args.precision]
+    prec = {"fp64": PREC_FP64, "tiered": PREC_TIERED, "fp32": PREC_FP32, "bf16x3": hfx.PREC_BF16X3}[args.precision]
     sched_kind = {"lpt": hfx.SCHED_LPT, "plan": hfx.SCHED_PLAN, "exact": hfx.SCHED_EXACT, "norm": hfx.SCHED_NORM,
                   "kmeans": hfx.SCHED_KMEANS}[args.scheduler]
-    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau, use_graph=args.graph,
-                scheduler=sched_kind)
+    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau, tier_tau_bf=args.tau_bf,
+                use_graph=args.graph, scheduler=sched_kind, tuning_db=args.tuning_db)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     progress(f"plan created in {t_plan:.1f}s")
@@ -309,10 +356,12 @@ def main():
     fl_alg = st["flops_contract"]
     ms_k = sum(ms_main) / len(ms_main)
     value = fl_paper / (ms_step / 1e3) / 1e12
-    # matrix-core peak of the mix: FP64 and FP32 shares of the contraction FLOPs at their own peaks
-    f32 = st["flops_tier"][1]
-    f64 = fl_alg - f32
-    peak = fl_alg / (f64 / FP64_PEAK_TF + f32 / FP32_PEAK_TF) if fl_alg > 0 else FP64_PEAK_TF
+    # matrix-core peak of the mix: the FP64, FP32 and split-BF16x3 shares of the contraction FLOPs at
+    # their own peaks
+    f32, fbf = st["flops_tier"][1], st["flops_tier"][2]
+    f64 = fl_alg - f32 - fbf
+    peak = (fl_alg / (f64 / FP64_PEAK_TF + f32 / FP32_PEAK_TF + fbf / BF16X3_PEAK_TF) if fl_alg > 0
+            else FP64_PEAK_TF)
     # achieved: the same Algorithm-3 count as `value` per average main-kernel launch; the library's
     # own (re-associated, smaller) count is reported beside it
     achieved = fl_paper / (ms_k / 1e3) / 1e12
@@ -321,12 +370,18 @@ def main():
         "metric": METRIC, "value": round(value, 4), "unit": "TFLOP/s (Alg.3-equivalent)", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
         "build_s": round(ms_step / 1e3, 4), "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "tiered": "f64+f32", "fp32": "f32 (f64 accumulation)"}[args.precision],
+        "dtype": {"fp64": "f64", "tiered": "f64+f32", "fp32": "f32 (f64 accumulation)",
+                  "bf16x3": "f64+f32+bf16x3"}[args.precision],
         "data": "synthetic (seeded keyed blocks, hfx_synth)",
         "config": {"workload": WORKLOADS[args.workload].format(eps=eps, precision=args.precision),
                    "eps": eps, "n_atoms": n_atoms, "precision": args.precision, "scheduler": args.scheduler,
                    "tier_tau": args.tau if args.precision == "tiered" else None, "hip_graph": args.graph},
         "flops_fp32_share": round(f32 / fl_alg, 4) if fl_alg > 0 else 0.0,
+        "tiles": {"terms34_block": f"128x{st['tile_r']}x16", "terms12_block": "128x64x16",
+                  "tile_r": st["tile_r"], "tier_tau": st["tier_tau"], "tier_tau_bf": st["tier_tau_bf"],
+                  "tuning_db": os.path.relpath(args.tuning_db, ROOT) if args.tuning_db else None},
+        "mfma_flops_issued_by_phase": {"gside_masks": st["mfma_flops"][0], "terms34": st["mfma_flops"][1],
+                                       "terms12": st["mfma_flops"][2]},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": round(peak, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": measured_traffic(args.eps) if (args.precision == "fp64" and args.workload == "cfg3")
@@ -351,7 +406,8 @@ def main():
         out["density"] = density_step(args.eps, args.fourier_reps)
     if args.precision == "fp64" and args.mixed_steps > 0:
         del plan
-        out["mixed"] = mixed_form(w, D, sigma, e_x, ms_step, args)
+        out["mixed"] = mixed_form(w, D, sigma, e_x, ms_step, args, "tiered")
+        out["mixed_bf16x3"] = mixed_form(w, D, sigma, e_x, ms_step, args, "bf16x3")
     if not args.no_cpu_baseline:
         nt = args.cpu_threads or host_cpu()[2]
         out["cpu_baseline"] = cpu_baseline(args.eps, fl_paper / n_atoms, nt)

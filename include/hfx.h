@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define HFX_ABI_VERSION 2
+#define HFX_ABI_VERSION 3
 
 typedef enum {
   HFX_OK = 0,
@@ -107,8 +107,12 @@ typedef struct {             /* Sec. III B and III C; 0 keeps every non-zero bou
 #define HFX_PREC_FP32 1     /* every block product on FP32 MFMA (FP32 operands and sums)   */
 #define HFX_PREC_TIERED 2   /* a block product runs on FP32 MFMA when the stage-2 bound of
                                every kept unit in it is <= tier_tau, else in FP64           */
-#define HFX_PREC_BF16X3 3   /* split-BF16x3: not available, hfx_plan_create returns
-                               HFX_ERR_UNSUPPORTED                                          */
+#define HFX_PREC_BF16X3 3   /* three tiers: as HFX_PREC_TIERED, and a terms-3/4 block product
+                               whose kept units all have a stage-2 bound <= tier_tau_bf runs
+                               as split-BF16x3 (each FP32 operand split as hi + lo in BF16,
+                               hi*hi + hi*lo + lo*hi on the BF16 matrix cores with FP32 sums,
+                               about 2^-16 relative error); the terms-1/2 product's lowest
+                               tier stays FP32                                              */
 
 #define HFX_SCREEN_PRE 1u    /* block max-abs pre-screening of C, V, D                     */
 #define HFX_SCREEN_CS_ERI 2u /* CS-ERI quartet test                                        */
@@ -141,8 +145,10 @@ typedef struct {
   int32_t precision;          /* HFX_PREC_*                                                 */
   uint32_t stages;            /* HFX_SCREEN_* bitmask; 0 means HFX_SCREEN_ALL               */
   double tier_tau;            /* TIERED: a block product whose kept units all have a stage-2
-                                 bound <= tier_tau runs on FP32 MFMA (finite, >= 0)         */
-  double tier_tau_bf;         /* reserved for split-BF16x3 (not available); ignored         */
+                                 bound <= tier_tau runs on FP32 MFMA (finite, >= 0; < 0: the
+                                 value the tuning file holds for this plan)                 */
+  double tier_tau_bf;         /* BF16X3: bound of the split-BF16x3 tier (<= tier_tau; < 0: the
+                                 tuning file's value)                                      */
   int32_t scheduler;          /* HFX_SCHED_*                                                */
   const char *mlp_weights;    /* file written by the scheduler trainer, or NULL             */
   void *stream;               /* hipStream_t for plan-time and build work; NULL = default   */
@@ -156,6 +162,12 @@ typedef struct {
                                  device-side build (D gather, D screening, Sigma clear,
                                  persistent kernel, Sigma copy-out); needs D on the device;
                                  the graph is re-captured when the D or Sigma pointers change */
+  const char *tuning_db;      /* text file written by the autotuner, or NULL: one choice per line,
+                                   hfxtune1 <key> tile_r=<32|64> tier_tau=<x> tier_tau_bf=<x>
+                                 where <key> is hfx_tune_key's string of the plan; the last
+                                 line with the plan's key is used                            */
+  int32_t tile_r;             /* column width of the output blocks of the terms-3/4 product:
+                                 32 or 64; 0: the tuning file's choice, else 64             */
 } hfx_options;
 
 typedef struct {               /* filled by hfx_build when non-NULL (synchronises)          */
@@ -168,9 +180,9 @@ typedef struct {               /* filled by hfx_build when non-NULL (synchronise
                                   the kept units (padding and screened-out work excluded)   */
   double flops_paper;          /* FLOPs of the same kept units counted as in Algorithm 3:
                                   T and Htilde per unit, Y, T3, T4 once per (A,B,G)          */
-  double flops_tier[3];        /* flops_contract split by precision: FP64 / FP32 / BF16x3; the
-                                  FP32 part is flops_contract times the FP32 share of the
-                                  matrix-core instructions issued                           */
+  double flops_tier[3];        /* flops_contract split by precision: FP64 / FP32 / BF16x3, by the
+                                  precision shares of the block products issued (a split-BF16x3
+                                  16x16x32 product counts as 16 FP32 16x16x4 ones)          */
   double mfma_flops[3];        /* matrix-core FLOPs issued (with padding): G side and masks,
                                   terms 3+4, terms 1+2                                       */
   double ms_total;             /* device time of the build (events on the plan stream)      */
@@ -180,6 +192,10 @@ typedef struct {               /* filled by hfx_build when non-NULL (synchronise
                                   Y = VC and the G-side products, stage-2/3 masks, terms 3+4,
                                   terms 1+2, item set-up                                     */
   double mfma_flops_fp32;      /* part of mfma_flops issued on the FP32 matrix cores         */
+  int32_t tile_r;              /* column width of the terms-3/4 output blocks the build used */
+  int32_t pad;
+  double tier_tau, tier_tau_bf; /* precision-tier bounds the build used                     */
+  double mfma_flops_bf16;      /* part of mfma_flops issued on the BF16 matrix cores (split-BF16x3) */
 } hfx_build_stats;
 
 typedef struct hfx_plan hfx_plan;
@@ -328,6 +344,12 @@ hfx_status hfx_mlp_train_static(int32_t n_in, int32_t n_hidden, int32_t n_out, f
  * output 0 of the model applied to these features of the previous build (its
  * first build uses HFX_SCHED_LPT order).  Synchronises. */
 hfx_status hfx_item_features(hfx_plan *plan, const float *mu, const float *sd, float *X);
+
+/* The key under which the autotuner files its choices for this plan: the species present (n_ao x
+ * n_abf, sorted, '+'-joined), the CS-matrix threshold and the precision form, e.g.
+ *   "species=13x60 eps=1e-06 prec=tiered"
+ * written into buf (len bytes, NUL-terminated).  HFX_ERR_ARG if buf is too small. */
+hfx_status hfx_tune_key(const hfx_plan *plan, char *buf, int32_t len);
 
 void hfx_plan_destroy(hfx_plan *plan);
 const char *hfx_last_error(void);

@@ -20,11 +20,11 @@ SCHED_PLAN, SCHED_LPT, SCHED_MLP, SCHED_EXACT, SCHED_NORM, SCHED_KMEANS = 0, 1, 
 EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "hfx_item_profile",
             "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",
             "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features", "hfx_sigma_to_k",
-            "hfx_density_from_k", "hfx_mlp_train_static"]
+            "hfx_density_from_k", "hfx_mlp_train_static", "hfx_tune_key"]
 ITEM_UNITS = 5
 ITEM_FEATURES = 10
 ITEM_TARGETS = 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class Species(ctypes.Structure):
@@ -52,7 +52,7 @@ class Options(ctypes.Structure):
                 ("tier_tau_bf", ctypes.c_double), ("scheduler", ctypes.c_int32), ("mlp_weights", ctypes.c_char_p),
                 ("stream", ctypes.c_void_p), ("home_subset", ctypes.c_void_p), ("n_home_subset", ctypes.c_int32),
                 ("max_device_bytes", ctypes.c_uint64), ("n_slots", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("tuning_db", ctypes.c_char_p), ("tile_r", ctypes.c_int32)]
 
 
 class BuildStats(ctypes.Structure):
@@ -61,13 +61,17 @@ class BuildStats(ctypes.Structure):
                 ("flops_contract", ctypes.c_double), ("flops_paper", ctypes.c_double),
                 ("flops_tier", ctypes.c_double * 3), ("mfma_flops", ctypes.c_double * 3),
                 ("ms_total", ctypes.c_double), ("ms_main", ctypes.c_double),
-                ("phase_share", ctypes.c_double * 6), ("mfma_flops_fp32", ctypes.c_double)]
+                ("phase_share", ctypes.c_double * 6), ("mfma_flops_fp32", ctypes.c_double),
+                ("tile_r", ctypes.c_int32), ("pad", ctypes.c_int32), ("tier_tau", ctypes.c_double),
+                ("tier_tau_bf", ctypes.c_double), ("mfma_flops_bf16", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {"candidates": self.candidates, "kept_cs_eri": self.kept_cs_eri, "items": self.items,
              "g_alive": self.g_alive, "flops_contract": self.flops_contract, "flops_paper": self.flops_paper,
              "flops_tier": list(self.flops_tier), "mfma_flops": list(self.mfma_flops),
              "ms_total": self.ms_total, "ms_main": self.ms_main, "mfma_flops_fp32": self.mfma_flops_fp32,
+             "tile_r": self.tile_r, "tier_tau": self.tier_tau, "tier_tau_bf": self.tier_tau_bf,
+             "mfma_flops_bf16": self.mfma_flops_bf16,
              "phase_share": dict(zip(["screen", "gside", "masks", "gemm_r", "gemm_l", "setup"],
                                      [round(x, 4) for x in self.phase_share]))}
         for s in range(3):
@@ -126,6 +130,8 @@ def lib():
         L.hfx_mlp_train_static.restype = ctypes.c_int
         L.hfx_mlp_train_static.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_int64,
                                            ctypes.c_int32, ctypes.c_float, P, P]
+        L.hfx_tune_key.restype = ctypes.c_int
+        L.hfx_tune_key.argtypes = [P, ctypes.c_char_p, ctypes.c_int32]
         L.hfx_item_features.restype = ctypes.c_int
         L.hfx_item_features.argtypes = [P, P, P, P]
         L.hfx_sigma_to_k.restype = ctypes.c_int

@@ -99,7 +99,8 @@ enum {
   kCntPhase = 18,  // 6 entries: wall-clock ticks per phase, summed over items
   kCntMfmaR32 = 24,  // FP32 MFMA instructions issued, GEMM-R
   kCntMfmaL32 = 25,  // FP32 MFMA instructions issued, GEMM-L
-  kCntN = 26
+  kCntMfmaRbf = 26,  // BF16 MFMA instructions (16x16x32) issued, GEMM-R
+  kCntN = 27
 };
 
 constexpr int kItemUnits = 5;  // per item: kept units of terms 1..4, alive G

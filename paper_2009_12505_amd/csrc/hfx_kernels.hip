@@ -125,8 +125,9 @@ struct KParams {
   long long wave_doubles;  // size of one per-wave region
   long long wg_off;        // offset (doubles) of the workgroup region (GEMM-L panel, P block)
   long long ub_off;        // offset (doubles) of the per-(F,G) unit bounds used by the precision tiers
-  int tier;                // 0: FP64 block products; 1: FP32 for blocks whose bound <= tau; 2: all FP32
-  float tau;
+  int tier;                // 0: FP64 block products; 1: FP32 for blocks whose bound <= tau; 2: all FP32;
+                           // 3: as 1, and split-BF16x3 for term-3/4 blocks whose bound <= tau_bf
+  float tau, tau_bf;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -675,34 +676,35 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Workgroup block product: a 128-row x 64-column output block, K streamed through two LDS
-// stages in chunks of 16.  Each thread fetches four A elements (row tid&127) and two B
-// elements (column tid&63) of the next chunk into registers while the MFMAs of the current
-// chunk run, then stores them into the other stage; wave w owns row tile w and column
-// tiles 0..3 (act: which of the four to compute).
+// Workgroup block product: a 128-row x W-column output block (W = 64 or 32), K streamed through
+// two LDS stages in chunks of 16.  Each thread fetches four A elements (row tid&127) and W/32 B
+// elements (column tid%W) of the next chunk into registers while the MFMAs of the current chunk
+// run, then stores them into the other stage; wave w owns row tile w and the W/16 column tiles
+// (act: which of them to compute).
 // a_at(k) / b_at(k) return this thread's A / B element at k (0 outside the operands).
-constexpr int BM = 128, BN = 64, BK = 16;
+constexpr int BM = 128, BN = 64, BK = 16;  // BN: the widest block (stage sizes, terms 1 and 2)
 
-template <class AAt, class BAt>
+template <int W, class AAt, class BAt>
 __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned act, double *As, double *Bs,
-                                            d4 (&acc)[4]) {
-  // As, Bs: two stages each ([2][BK][BM], [2][BK][BN]); one barrier per chunk
+                                            d4 (&acc)[W / 16]) {
+  // As, Bs: two stages each ([2][BK][BM], [2][BK][W]); one barrier per chunk
+  constexpr int NV = W / 16, RS = NT / W, NBF = BK / RS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int ar = tid & (BM - 1), akq = (tid >> 7) << 2;
-  const int bc = tid & (BN - 1), bk = tid >> 6;
-  double ra[4], rb[2];
+  const int bc = tid & (W - 1), bk = tid / W;
+  double ra[4], rb[NBF];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0;
-    rb[0] = k0 + bk < K ? b_at(k0 + bk) : 0.0;
-    rb[1] = k0 + bk + 8 < K ? b_at(k0 + bk + 8) : 0.0;
+#pragma unroll
+    for (int q = 0; q < NBF; ++q) rb[q] = k0 + bk + q * RS < K ? b_at(k0 + bk + q * RS) : 0.0;
   };
   auto stash = [&](int st) {
-    double *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+    double *a = As + st * BK * BM, *b = Bs + st * BK * W;
 #pragma unroll
     for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = ra[s];
-    b[bk * BN + bc] = rb[0];
-    b[(bk + 8) * BN + bc] = rb[1];
+#pragma unroll
+    for (int q = 0; q < NBF; ++q) b[(bk + q * RS) * W + bc] = rb[q];
   };
   __syncthreads();  // the previous user of the stages is done
   fetch(0);
@@ -713,14 +715,14 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned 
     const bool more = k0 + BK < K;
     if (more) fetch(k0 + BK);
     if (act) {
-      const double *a = As + st * BK * BM, *b = Bs + st * BK * BN;
+      const double *a = As + st * BK * BM, *b = Bs + st * BK * W;
 #pragma unroll 2
       for (int s = 0; s < BK / 4; ++s) {
         const int kr = 4 * s + kk;
         const double av = a[kr * BM + wave * 16 + l16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (act & (1u << v)) acc[v] = mfma64(av, b[kr * BN + v * 16 + l16], acc[v]);
+        for (int v = 0; v < NV; ++v)
+          if (act & (1u << v)) acc[v] = mfma64(av, b[kr * W + v * 16 + l16], acc[v]);
       }
     }
     if (more) stash(st ^ 1);
@@ -739,27 +741,27 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned 
 constexpr int BKF = 16;
 static_assert(BKF * (BM + BN) * 4 <= BK * (BM + BN) * 8, "FP32 stages reuse the FP64 stage buffers");
 
-template <class AAt, class BAt>
+template <int W, class AAt, class BAt>
 __device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, unsigned act, float *As, float *Bs,
-                                              f4 (&acc)[4]) {
-  constexpr int NA = BKF / 4, NB = BKF / 8;
+                                              f4 (&acc)[W / 16]) {
+  constexpr int NV = W / 16, RS = NT / W, NA = BKF / 4, NB = BKF / RS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int ar = tid & (BM - 1), akq = (tid >> 7) * NA;
-  const int bc = tid & (BN - 1), bk = tid >> 6;
+  const int bc = tid & (W - 1), bk = tid / W;
   float ra[NA];
   double rb[NB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < NA; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0f;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) rb[q] = k0 + bk + 8 * q < K ? b_at(k0 + bk + 8 * q) : 0.0;
+    for (int q = 0; q < NB; ++q) rb[q] = k0 + bk + RS * q < K ? b_at(k0 + bk + RS * q) : 0.0;
   };
   auto stash = [&](int st) {
-    float *a = As + st * BKF * BM, *b = Bs + st * BKF * BN;
+    float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
 #pragma unroll
     for (int s = 0; s < NA; ++s) a[(akq + s) * BM + ar] = ra[s];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) b[(bk + 8 * q) * BN + bc] = (float)rb[q];
+    for (int q = 0; q < NB; ++q) b[(bk + RS * q) * W + bc] = (float)rb[q];
   };
   __syncthreads();  // the previous user of the stages is done
   fetch(0);
@@ -770,14 +772,90 @@ __device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, unsigne
     const bool more = k0 + BKF < K;
     if (more) fetch(k0 + BKF);
     if (act) {
-      const float *a = As + st * BKF * BM, *b = Bs + st * BKF * BN;
+      const float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
 #pragma unroll 2
       for (int s = 0; s < BKF / 4; ++s) {
         const int kr = 4 * s + kk;
         const float av = a[kr * BM + wave * 16 + l16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (act & (1u << v)) acc[v] = mfma32(av, b[kr * BN + v * 16 + l16], acc[v]);
+        for (int v = 0; v < NV; ++v)
+          if (act & (1u << v)) acc[v] = mfma32(av, b[kr * W + v * 16 + l16], acc[v]);
+      }
+    }
+    if (more) stash(st ^ 1);
+    __syncthreads();
+    st ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Split-BF16x3 block product (the lowest precision tier of terms 3 and 4): every FP32 operand is
+// split as x = hi + lo with hi = bf16(x) and lo = bf16(x - hi) (round to nearest even), and the
+// product is accumulated in FP32 as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 (lane l
+// supplies row l%16 of A and column l%16 of B at k = 8(l/16)..8(l/16)+7; the result layout is the
+// FP32 form's).  The dropped lo*lo term and the rounding of lo leave about 2^-16 relative error
+// per product.  K is streamed in chunks of 32 through two LDS stages holding hi and lo rows with
+// k contiguous.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int BKB = 32;
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <int W, class AAt, class BAt>
+__device__ __forceinline__ void wg_block_mm_bf3(int K, AAt a_at, BAt b_at, unsigned act, uint16_t *As, uint16_t *Bs,
+                                                f4 (&acc)[W / 16]) {
+  constexpr int NV = W / 16, KB = BKB * W / NT;  // B elements per thread and chunk (4 or 2)
+  constexpr int ASZ = 2 * BM * BKB, BSZ = 2 * W * BKB;  // one stage: hi block then lo block
+  static_assert(2 * ASZ * 2 <= 2 * BK * BM * 8 && 2 * BSZ * 2 <= 2 * BK * BN * 8, "BF16 stages fit the FP64 ones");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kg = lane >> 4, l16 = lane & 15;
+  const int ar = tid & (BM - 1), ako = (tid >> 7) * 8;
+  const int bc = tid & (W - 1), bko = (tid / W) * KB;
+  float ra[8], rb[KB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) ra[s] = (k0 + ako + s < K) ? a_at(k0 + ako + s) : 0.0f;
+#pragma unroll
+    for (int q = 0; q < KB; ++q) rb[q] = (k0 + bko + q < K) ? (float)b_at(k0 + bko + q) : 0.0f;
+  };
+  auto stash = [&](int st) {
+    uint16_t *a = As + st * ASZ, *b = Bs + st * BSZ;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const uint16_t h = bf16_rne(ra[s]);
+      a[ar * BKB + ako + s] = h;
+      a[BM * BKB + ar * BKB + ako + s] = bf16_rne(ra[s] - bf16_val(h));
+    }
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const uint16_t h = bf16_rne(rb[q]);
+      b[bc * BKB + bko + q] = h;
+      b[W * BKB + bc * BKB + bko + q] = bf16_rne(rb[q] - bf16_val(h));
+    }
+  };
+  __syncthreads();  // the previous user of the stages is done
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int st = 0;
+  for (int k0 = 0; k0 < K; k0 += BKB) {
+    const bool more = k0 + BKB < K;
+    if (more) fetch(k0 + BKB);
+    if (act) {
+      const uint16_t *a = As + st * ASZ, *b = Bs + st * BSZ;
+      const bf8 ahi = *reinterpret_cast<const bf8 *>(a + (wave * 16 + l16) * BKB + kg * 8);
+      const bf8 alo = *reinterpret_cast<const bf8 *>(a + BM * BKB + (wave * 16 + l16) * BKB + kg * 8);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {  // every tile of an active wave (see the FP32 form)
+        const bf8 bhi = *reinterpret_cast<const bf8 *>(b + (v * 16 + l16) * BKB + kg * 8);
+        const bf8 blo = *reinterpret_cast<const bf8 *>(b + W * BKB + (v * 16 + l16) * BKB + kg * 8);
+        acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[v], 0, 0, 0);
+        acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[v], 0, 0, 0);
+        acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[v], 0, 0, 0);
       }
     }
     if (more) stash(st ^ 1);
@@ -816,14 +894,18 @@ __device__ __forceinline__ bool tile_has(const ItemLds &L, const uint8_t *mask, 
 // GEMM-R: terms 3 and 4.  Rows (F,f), K = (alpha,a), columns (G, [g | b]):
 //   out[(F,f)][(G,g)] = sum_{al,a} C_AF[al][a][f] T4_G[al][a][g]  -> Sigma(F,G)  (term 4)
 //   out[(F,f)][(G,b)] = sum_{al,a} C_AF[al][a][f] T3_G[al][a][b]  -> summed over G into Sigma(F,B)
-// 128 x 64 blocks in row-block-major order; a block whose 32 tiles hold no kept unit is skipped.
+// 128 x W blocks (W = 64 or 32, the plan's tile_r) in row-block-major order; a block whose tiles
+// hold no kept unit is skipped.
+template <int W, bool BF>
 __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
                              const uint8_t *row2i, const short *col2jj, double *As, double *Bs, double *acc3,
-                             int ld3, const float *ub, int tier, float tau) {
+                             int ld3, const float *ub, int tier, float tau, float tau_bf) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int K = L.PA * L.na, nb = L.nb;
-  const int nrb = (L.MR + BM - 1) / BM, ncb = (L.NR + BN - 1) / BN;
-  unsigned long long nmfma = 0, nmfma32 = 0;
+  const bool tiered = tier == 1 || tier == 3;
+  constexpr int NCT = W / 16;  // column tiles per block
+  const int nrb = (L.MR + BM - 1) / BM, ncb = (L.NR + W - 1) / W;
+  unsigned long long nmfma = 0, nmfma32 = 0, nmfmabf = 0;
   for (int rb = 0; rb < nrb; ++rb) {
     for (int q = lane; q < 16 * ld3; q += 64) acc3[q] = 0.0;
     bool any3 = false;
@@ -841,23 +923,25 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
         L.blk_ub = 0u;
       }
       __syncthreads();
-      {
-        const int sidx = tid >> 4, wr = sidx >> 2, ct = sidx & 3;
+      if (tid < 8 * NCT * 16) {
+        const int sidx = tid >> 4, wr = sidx / NCT, ct = sidx % NCT;
         const int rr = rb * BM + wr * 16 + (tid & 15);
         if (rr < L.MR) {
-          const int c_lo = cb * BN + ct * 16, c_hi = min(c_lo + 16, L.NR);
+          const int c_lo = cb * W + ct * 16, c_hi = min(c_lo + 16, L.NR);
           if (tile_has(L, mask, col2jj, row2i[rr], c_lo, c_hi, kT4, kT3)) {
             atomicOr(&L.blk_act, 1u << sidx);
-            if (tier == 1) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, row2i[rr], c_lo, c_hi, 1)));
+            if (tiered) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, row2i[rr], c_lo, c_hi, 1)));
           }
         }
       }
       __syncthreads();
       const unsigned act_all = L.blk_act;
       if (!act_all) continue;
-      const bool fp32 = tier == 2 || (tier == 1 && __uint_as_float(L.blk_ub) <= tau);
-      const unsigned act = (act_all >> (4 * wave)) & 15u;
-      const int c = cb * BN + (tid & (BN - 1));
+      const float bub = __uint_as_float(L.blk_ub);
+      const bool bf = BF && tier == 3 && bub <= tau_bf;
+      const bool fp32 = bf || tier == 2 || (tiered && bub <= tau);
+      const unsigned act = (act_all >> (NCT * wave)) & ((1u << NCT) - 1u);
+      const int c = cb * W + (tid & (W - 1));
       const bool cok = c < L.NR;
       const double *Bb = slot;
       int Bstr = 0;
@@ -872,33 +956,50 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
           Bstr = nb;
         }
       }
-      d4 acc[4];
-      if (fp32) {
-        f4 a32[4];
+      d4 acc[NCT];
+      if constexpr (BF) {
+        if (bf) {
+          f4 a32[NCT];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) a32[v] = f4{0, 0, 0, 0};
-        wg_block_mm32(
+          for (int v = 0; v < NCT; ++v) a32[v] = f4{0, 0, 0, 0};
+          wg_block_mm_bf3<W>(
+              K, [&](int k) { return rok ? Ab32[(long long)k * As_] : 0.0f; },
+              [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, reinterpret_cast<uint16_t *>(As),
+              reinterpret_cast<uint16_t *>(Bs), a32);
+          nmfmabf += (unsigned long long)(act ? 3 * NCT : 0) * ((K + BKB - 1) / BKB);
+#pragma unroll
+          for (int v = 0; v < NCT; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[v][e] = (double)a32[v][e];
+        }
+      }
+      if (bf) {
+      } else if (fp32) {
+        f4 a32[NCT];
+#pragma unroll
+        for (int v = 0; v < NCT; ++v) a32[v] = f4{0, 0, 0, 0};
+        wg_block_mm32<W>(
             K, [&](int k) { return rok ? Ab32[(long long)k * As_] : 0.0f; },
             [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, reinterpret_cast<float *>(As),
             reinterpret_cast<float *>(Bs), a32);
         nmfma32 += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < NCT; ++v)
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc[v][e] = (double)a32[v][e];
       } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
-        wg_block_mm(
+        for (int v = 0; v < NCT; ++v) acc[v] = d4{0, 0, 0, 0};
+        wg_block_mm<W>(
             K, [&](int k) { return rok ? Ab[(long long)k * As_] : 0.0; },
             [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, As, Bs, acc);
         nmfma += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
       }
       // epilogue of this wave's tiles
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      for (int v = 0; v < NCT; ++v) {
         if (!(act & (1u << v))) continue;
-        const int cc0 = cb * BN + v * 16 + l16;
+        const int cc0 = cb * W + v * 16 + l16;
         if (cc0 >= L.NR) continue;
         const int jj = col2jj[cc0], j = L.a_j[jj];
         const int cc = cc0 - L.a_col0[jj], ng = L.g_n[j];
@@ -934,6 +1035,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
   }
   if (lane == 0 && nmfma) atomicAdd(&L.cnt[kCntMfmaR], nmfma);
   if (lane == 0 && nmfma32) atomicAdd(&L.cnt[kCntMfmaR32], nmfma32);
+  if (lane == 0 && nmfmabf) atomicAdd(&L.cnt[kCntMfmaRbf], nmfmabf);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1071,12 +1173,12 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
           const int cl = c0 + ct * 16;
           if (tile_has(L, mask, col2jj, i, cl, min(cl + 16, c1), kT1, kT2)) atomicOr(&L.blk_act, 1u << ct);
         }
-        if (tier == 1) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, i, c0, c1, 0)));
+        if (tier == 1 || tier == 3) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, i, c0, c1, 0)));
       }
     }
     __syncthreads();
     if (!L.blk_act) continue;
-    const bool fp32 = tier == 2 || (tier == 1 && __uint_as_float(L.blk_ub) <= tau);
+    const bool fp32 = tier == 2 || ((tier == 1 || tier == 3) && __uint_as_float(L.blk_ub) <= tau);
     if (tid == 0) {
       int kc = 0, m = 0;
       for (int i = 0; i < nF; ++i)
@@ -1138,7 +1240,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
         f4 a32[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) a32[v] = f4{0, 0, 0, 0};
-        wg_block_mm32(
+        wg_block_mm32<BN>(
             Kc,
             [&](int k) {
               const long long ka = kaddr[k];
@@ -1154,7 +1256,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
-        wg_block_mm(
+        wg_block_mm<BN>(
             Kc,
             [&](int k) {
               const long long ka = kaddr[k];
@@ -1186,6 +1288,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
 }
 
 // ---------------------------------------------------------------------------------------------
+template <int W, bool BF>
 __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
   __shared__ ItemLds L;
   extern __shared__ double dyn[];
@@ -1363,7 +1466,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       __syncthreads();
     }
     tick(1);
-    float *ub = kp.tier == 1 ? reinterpret_cast<float *>(slot + kp.ub_off) : nullptr;
+    float *ub = (kp.tier == 1 || kp.tier == 3) ? reinterpret_cast<float *>(slot + kp.ub_off) : nullptr;
     phase_masks(P, L, slot, dfg, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
@@ -1418,8 +1521,8 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     __syncthreads();
     tick(2);
     if (L.nGa > 0) {
-      phase_gemm_r(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
-                   kp.tier, kp.tau);
+      phase_gemm_r<W, BF>(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
+                   kp.tier, kp.tau, kp.tau_bf);
       __syncthreads();
       tick(3);
       phase_gemm_l(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr, ub, kp.tier,
@@ -1734,19 +1837,33 @@ hipError_t launch_to_f32(const double *src, float *dst, long long n, hipStream_t
 
 hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3) {
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
-  return hipFuncSetAttribute((const void *)k_main, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+  const void *fns[] = {(const void *)k_main<64, false>, (const void *)k_main<32, false>,
+                       (const void *)k_main<64, true>, (const void *)k_main<32, true>};
+  for (const void *f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
-                       long long wave_doubles, long long wg_off, long long ub_off, int tier, float tau, hipStream_t s,
-                       bool set_lds) {
-  KParams kp{rows_cap, cols_cap, ld3, wave_off, wave_doubles, wg_off, ub_off, tier, tau};
+                       long long wave_doubles, long long wg_off, long long ub_off, int tier, float tau, float tau_bf,
+                       int tile_r, hipStream_t s, bool set_lds) {
+  KParams kp{rows_cap, cols_cap, ld3, wave_off, wave_doubles, wg_off, ub_off, tier, tau, tau_bf};
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
   if (set_lds) {
     hipError_t e = main_set_lds(rows_cap, cols_cap, ld3);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_main, dim3(n_slots), dim3(NT), dyn, s, P, kp);
+  const bool bf = tier == 3;
+  if (tile_r == 32 && bf)
+    hipLaunchKernelGGL((k_main<32, true>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
+  else if (tile_r == 32)
+    hipLaunchKernelGGL((k_main<32, false>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
+  else if (bf)
+    hipLaunchKernelGGL((k_main<64, true>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
+  else
+    hipLaunchKernelGGL((k_main<64, false>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
   return hipGetLastError();
 }
 

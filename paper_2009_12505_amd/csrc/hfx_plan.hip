@@ -22,8 +22,8 @@
 
 namespace hfx {
 hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap, int ld3, long long wave_off,
-                       long long wave_doubles, long long wg_off, long long ub_off, int tier, float tau, hipStream_t s,
-                       bool set_lds);
+                       long long wave_doubles, long long wg_off, long long ub_off, int tier, float tau, float tau_bf,
+                       int tile_r, hipStream_t s, bool set_lds);
 hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3);
 hipError_t launch_to_f32(const double *src, float *dst, long long n, hipStream_t s);
 size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3);
@@ -197,6 +197,9 @@ struct hfx_plan {
   long long wave_off = 0, wave_doubles = 0, wg_off = 0, ub_off = 0;
   int tier = 0;       // 0: FP64 block products; 1: bound-tiered FP32; 2: all FP32
   float tau = 0.0f;
+  double tau64 = 0.0, tau_bf = 0.0;  // tier bounds as given or tuned (reported in the stats)
+  int tile_r = 64;                   // column width of the terms-3/4 output blocks
+  std::string tune_key;
   double *part = nullptr;  // energy partial sums
   // learned scheduler
   bool have_profile = false;
@@ -389,6 +392,13 @@ static hfx_status upload_packed(hfx_plan *p, double *dst, const std::vector<std:
 extern "C" {
 
 int32_t hfx_abi_version(void) { return HFX_ABI_VERSION; }
+
+hfx_status hfx_tune_key(const hfx_plan *p, char *buf, int32_t len) {
+  if (!p || !buf || len < 1) return fail(HFX_ERR_ARG, "NULL argument or empty buffer");
+  if ((int64_t)p->tune_key.size() + 1 > len) return fail(HFX_ERR_ARG, "buffer of %d bytes too small", len);
+  std::memcpy(buf, p->tune_key.c_str(), p->tune_key.size() + 1);
+  return HFX_OK;
+}
 const char *hfx_last_error(void) { return g_err.c_str(); }
 
 void hfx_plan_destroy(hfx_plan *plan) { delete plan; }
@@ -405,12 +415,11 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     if (!std::isfinite(e) || e < 0) return fail(HFX_ERR_ARG, "thresholds must be finite and >= 0");
   hfx_options o{};
   if (opt) o = *opt;
-  if (o.precision == HFX_PREC_BF16X3)
-    return fail(HFX_ERR_UNSUPPORTED, "split-BF16x3 block products are not implemented");
-  if (o.precision < HFX_PREC_FP64 || o.precision > HFX_PREC_TIERED)
+  if (o.precision < HFX_PREC_FP64 || o.precision > HFX_PREC_BF16X3)
     return fail(HFX_ERR_ARG, "unknown precision %d", o.precision);
-  if (o.precision == HFX_PREC_TIERED && !(o.tier_tau >= 0 && std::isfinite(o.tier_tau)))
-    return fail(HFX_ERR_ARG, "tier_tau must be finite and >= 0");
+  if (!std::isfinite(o.tier_tau) || !std::isfinite(o.tier_tau_bf))
+    return fail(HFX_ERR_ARG, "tier_tau must be finite and >= 0 (or < 0 to take it from the tuning file)");
+  if (o.tile_r != 0 && o.tile_r != 32 && o.tile_r != 64) return fail(HFX_ERR_ARG, "tile_r must be 0, 32 or 64");
   if (o.scheduler < HFX_SCHED_PLAN || o.scheduler > HFX_SCHED_KMEANS)
     return fail(HFX_ERR_ARG, "unknown scheduler %d", o.scheduler);
   if (o.scheduler == HFX_SCHED_MLP && !o.mlp_weights)
@@ -422,8 +431,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   p->th = *th;
   p->stages = o.stages ? o.stages : HFX_SCREEN_ALL;
   p->precision = o.precision;
-  p->tier = o.precision == HFX_PREC_TIERED ? 1 : o.precision == HFX_PREC_FP32 ? 2 : 0;
-  p->tau = (float)o.tier_tau;
+  p->tier = o.precision == HFX_PREC_TIERED ? 1 : o.precision == HFX_PREC_FP32 ? 2 : o.precision == HFX_PREC_BF16X3 ? 3 : 0;
   p->scheduler = o.scheduler;
   p->stream = (hipStream_t)o.stream;
   p->max_bytes = o.max_device_bytes;
@@ -455,6 +463,58 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     }
   }
   const int NA = p->atom_off[n_cells];
+
+  // ---- autotuner's choices: the plan's key and, if a tuning file is given, its last entry for it
+  {
+    std::vector<std::pair<int, int>> spc;
+    for (int a = 0; a < NA; ++a) spc.emplace_back(p->nao[a], p->nabf[a]);
+    std::sort(spc.begin(), spc.end());
+    spc.erase(std::unique(spc.begin(), spc.end()), spc.end());
+    std::string k = "species=";
+    for (size_t q = 0; q < spc.size(); ++q)
+      k += (q ? "+" : "") + std::to_string(spc[q].first) + "x" + std::to_string(spc[q].second);
+    char eb[64];
+    std::snprintf(eb, sizeof(eb), " eps=%.3g prec=%s", th->eps_cs_mat,
+                  o.precision == HFX_PREC_TIERED   ? "tiered"
+                  : o.precision == HFX_PREC_FP32   ? "fp32"
+                  : o.precision == HFX_PREC_BF16X3 ? "bf16x3"
+                                                   : "fp64");
+    p->tune_key = k + eb;
+    int t_tile = 0;
+    double t_tau = -1.0, t_tau_bf = -1.0;
+    if (o.tuning_db) {
+      FILE *fp = std::fopen(o.tuning_db, "r");
+      if (!fp) return fail(HFX_ERR_ARG, "cannot open tuning_db '%s'", o.tuning_db);
+      char line[1024];
+      while (std::fgets(line, sizeof(line), fp)) {
+        std::string ln(line);
+        if (ln.rfind("hfxtune1 ", 0) != 0) continue;
+        const size_t at = ln.find(" tile_r=");
+        if (at == std::string::npos || ln.substr(9, at - 9) != p->tune_key) continue;
+        int tr = 0;
+        double ta = -1.0, tb = -1.0;
+        if (std::sscanf(ln.c_str() + at, " tile_r=%d tier_tau=%lf tier_tau_bf=%lf", &tr, &ta, &tb) == 3) {
+          t_tile = tr;
+          t_tau = ta;
+          t_tau_bf = tb;
+        }
+      }
+      std::fclose(fp);
+      if (t_tile != 0 && t_tile != 32 && t_tile != 64)
+        return fail(HFX_ERR_ARG, "tuning_db '%s': tile_r %d for '%s' is not 32 or 64", o.tuning_db, t_tile,
+                    p->tune_key.c_str());
+    }
+    p->tile_r = o.tile_r ? o.tile_r : (t_tile ? t_tile : 64);
+    p->tau64 = o.tier_tau >= 0 ? o.tier_tau : t_tau;
+    p->tau_bf = o.tier_tau_bf >= 0 ? o.tier_tau_bf : t_tau_bf;
+    if ((o.precision == HFX_PREC_TIERED || o.precision == HFX_PREC_BF16X3) && p->tau64 < 0)
+      return fail(HFX_ERR_ARG, "tier_tau < 0 needs a tuning_db entry for '%s'", p->tune_key.c_str());
+    if (o.precision == HFX_PREC_BF16X3 && p->tau_bf < 0)
+      return fail(HFX_ERR_ARG, "tier_tau_bf < 0 needs a tuning_db entry for '%s'", p->tune_key.c_str());
+    p->tau64 = std::max(p->tau64, 0.0);
+    p->tau_bf = std::max(p->tau_bf, 0.0);
+    p->tau = (float)p->tau64;
+  }
 
   // home set
   std::vector<uint8_t> is_home(NA, o.home_subset ? 0 : 1);
@@ -767,7 +827,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   p->wg_off = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
   const int64_t wg_doubles = (int64_t)p->rows_cap * 64 + (int64_t)max_p * max_n * 64 + 64;
   p->ub_off = p->wg_off + wg_doubles;
-  const int64_t slot = p->ub_off + (p->tier == 1 ? nfg : 0);  // two float bounds per (F,G)
+  const int64_t slot = p->ub_off + ((p->tier == 1 || p->tier == 3) ? nfg : 0);  // two float bounds per (F,G)
   (void)min_n;
   p->ld3 = max_n;
   const size_t lds = main_static_lds() + main_dyn_lds(p->rows_cap, p->cols_cap, p->ld3);
@@ -1051,8 +1111,9 @@ static hfx_status enqueue_core(hfx_plan *p, double *const *sigma, bool eager) {
   HIPCHK(p, launch_zero(P.Sbuf, ntot, p->stream));
   HIPCHK(p, launch_reset(P.ticket, P.counters, P.flops, p->stream));
   if (eager) HIPCHK(p, hipEventRecord(p->ev1, p->stream));
-  if (p->n_items > 0) HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles,
-                                          p->wg_off, p->ub_off, p->tier, p->tau, p->stream, eager));
+  if (p->n_items > 0)
+    HIPCHK(p, launch_main(P, p->n_slots, p->rows_cap, p->cols_cap, p->ld3, p->wave_off, p->wave_doubles, p->wg_off,
+                          p->ub_off, p->tier, p->tau, (float)p->tau_bf, p->tile_r, p->stream, eager));
   if (eager) HIPCHK(p, hipEventRecord(p->ev2, p->stream));
   for (int c = 0; c < p->n_cells; ++c) {
     const size_t n = (size_t)(p->sbase[c + 1] - p->sbase[c]);
@@ -1171,18 +1232,27 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     HIPCHK(p, hipMemcpy(fl, P.flops, sizeof(fl), hipMemcpyDeviceToHost));
     stats->flops_paper = fl[0];
     stats->flops_contract = fl[1];
-    // matrix-core FLOPs issued (16x16x4 in either precision: 2048 each); the FP32 share of the
-    // contraction FLOPs is estimated by the FP32 share of the block-product instructions
+    // matrix-core FLOPs issued (16x16x4 in FP64 or FP32: 2048 each; the split-BF16x3 products:
+    // three 16x16x32 instructions, 16384 FLOPs each, per 16x16x32 FP32-equivalent product); the
+    // precision shares of the contraction FLOPs are estimated by the shares of these products
     const double mR = (double)cnt[kCntMfmaR], mL = (double)cnt[kCntMfmaL];
     const double mR32 = (double)cnt[kCntMfmaR32], mL32 = (double)cnt[kCntMfmaL32];
-    const double gemm = mR + mL + mR32 + mL32;
-    const double share32 = gemm > 0 ? (mR32 + mL32) / ((double)cnt[kCntMfmaY] + gemm) : 0.0;
+    const double mRbf = (double)cnt[kCntMfmaRbf];
+    const double eq_bf = mRbf * 16384.0 / 3.0;
+    const double issued = 2048.0 * ((double)cnt[kCntMfmaY] + mR + mL + mR32 + mL32) + eq_bf;
+    const double share32 = issued > 0 ? 2048.0 * (mR32 + mL32) / issued : 0.0;
+    const double sharebf = issued > 0 ? eq_bf / issued : 0.0;
     stats->flops_tier[1] = fl[1] * share32;
-    stats->flops_tier[0] = fl[1] - stats->flops_tier[1];
+    stats->flops_tier[2] = fl[1] * sharebf;
+    stats->flops_tier[0] = fl[1] - stats->flops_tier[1] - stats->flops_tier[2];
     stats->mfma_flops[0] = 2048.0 * (double)cnt[kCntMfmaY];
-    stats->mfma_flops[1] = 2048.0 * (mR + mR32);
+    stats->mfma_flops[1] = 2048.0 * (mR + mR32) + 16384.0 * mRbf;
     stats->mfma_flops[2] = 2048.0 * (mL + mL32);
     stats->mfma_flops_fp32 = 2048.0 * (mR32 + mL32);
+    stats->mfma_flops_bf16 = 16384.0 * mRbf;
+    stats->tile_r = p->tile_r;
+    stats->tier_tau = p->tier ? p->tau64 : 0.0;
+    stats->tier_tau_bf = p->tau_bf;
     float ms0 = 0, ms1 = 0;
     HIPCHK(p, hipEventElapsedTime(&ms0, p->ev0, p->ev2));
     HIPCHK(p, hipEventElapsedTime(&ms1, p->ev1, p->ev2));

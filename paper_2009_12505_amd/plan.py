@@ -49,7 +49,7 @@ class Plan:
 
     def __init__(self, cells, C, V, D_pattern, thresholds, precision=A.PREC_FP64, stages=A.SCREEN_ALL,
                  scheduler=A.SCHED_LPT, home_subset=None, stream=None, n_slots=0, max_device_bytes=0,
-                 tier_tau=0.0, tier_tau_bf=0.0, mlp_weights=None, use_graph=False):
+                 tier_tau=0.0, tier_tau_bf=0.0, mlp_weights=None, use_graph=False, tuning_db=None, tile_r=0):
         import torch
         self._torch = torch
         L = A.lib()
@@ -89,7 +89,8 @@ class Plan:
                         None if mlp_weights is None else str(mlp_weights).encode(),
                         ctypes.c_void_p(stream.cuda_stream), None if hs is None else hs.ctypes.data,
                         0 if hs is None else int(hs.shape[0]), int(max_device_bytes), int(n_slots),
-                        1 if use_graph else 0)
+                        1 if use_graph else 0, None if tuning_db is None else str(tuning_db).encode(),
+                        int(tile_r))
         h = ctypes.c_void_p()
         A.check(L.hfx_plan_create(self.n_cells, ctypes.byref(ccells), ctypes.byref(cC), ctypes.byref(cV),
                                   ctypes.byref(cD), ctypes.byref(th), ctypes.byref(opt), ctypes.byref(h)))
@@ -105,6 +106,9 @@ class Plan:
             self.layouts.append(off)
             self.sizes.append(int(n.value))
         self.last_stats = None
+        buf = ctypes.create_string_buffer(256)
+        A.check(L.hfx_tune_key(h, buf, 256))
+        self.tune_key = buf.value.decode()
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(A.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
-    assert L.hfx_abi_version() == 2
+    assert L.hfx_abi_version() == A.ABI_VERSION == 3
 
 
 def _cstructs(w, th=None):
@@ -127,13 +127,23 @@ def test_rejects_unknown_scheduler_and_null_out():
     assert L.hfx_build(None, None, None, None) == A.HFX_ERR_ARG
 
 
-def test_rejects_unavailable_or_invalid_precision():
+def test_rejects_invalid_precision_tiles_and_tuning():
     w = _tiny()
     keep, c, C, V, D, th = _cstructs(w)
     opt = A.Options()
     opt.precision = A.PREC_BF16X3
+    opt.tier_tau_bf = -1.0  # < 0 needs a tuning file entry
+    opt.tier_tau = 1e-3
     st, msg = _create(c, C, V, D, th, opt)
-    assert st == A.HFX_ERR_UNSUPPORTED and "BF16" in msg
+    assert st == A.HFX_ERR_ARG and "tier_tau_bf" in msg
+    opt = A.Options()
+    opt.tile_r = 48
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_ARG and "tile_r" in msg
+    opt = A.Options()
+    opt.tuning_db = b"/nonexistent/tuning.txt"
+    st, msg = _create(c, C, V, D, th, opt)
+    assert st == A.HFX_ERR_ARG and "tuning_db" in msg
     opt = A.Options()
     opt.precision = 7
     st, msg = _create(c, C, V, D, th, opt)
