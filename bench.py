@@ -165,6 +165,33 @@ def mixed_form(w, D, sigma64, e64, ms64, args, precision="tiered"):
     return out
 
 
+def graph_form(w, D, sigma64, ms64, args):
+    """The same FP64 build replayed as one captured HIP graph (the device-side build of every
+    step: D gather, D screening, Sigma clear, the persistent kernel, Sigma copy-out) beside the
+    eager build just timed; D in device memory, the graph captured by the warm-up build."""
+    import torch
+    from paper_2009_12505_amd import Plan
+    torch.cuda.empty_cache()
+    plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, use_graph=True, tuning_db=args.tuning_db)
+    sigma = plan.alloc_sigma()
+    plan.build(D, sigma)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.graph_steps):
+        plan.build(D, sigma)
+        progress("graph replay done")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.graph_steps
+    dsig = max(float((a - b).abs().max()) for a, b in zip(sigma, sigma64))
+    del plan, sigma
+    torch.cuda.empty_cache()
+    return {"steps": args.graph_steps, "build_s": round(ms / 1e3, 4), "eager_build_s": round(ms64 / 1e3, 4),
+            "ratio_graph_over_eager": round(ms / ms64, 4), "max_abs_dsigma_vs_eager": dsig}
+
+
 def fourier_sum(plan, sigma, reps: int):
     """The real-space to k-space sum of the FP64 Sigma just built at the eight k-points of the
     2x2x2 grid of the supercell's Brillouin zone (one launch): its time (HIP events on the plan
@@ -274,6 +301,8 @@ def main():
     ap.add_argument("--tune-homes", type=int, default=32, help="home atoms of the tuning subset")
     ap.add_argument("--graph", action="store_true",
                     help="replay the build as one captured HIP graph (kernel time = whole graph)")
+    ap.add_argument("--graph-steps", type=int, default=1,
+                    help="after an eager FP64 run: time this many replays of the build as one HIP graph (0: skip)")
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="after an FP64 run: time this many builds of the tiered form (tau = --tau) on the "
                          "same inputs and report them against the FP64 build (0: skip)")
@@ -400,10 +429,13 @@ def main():
     if args.workload != "cfg3":
         args.fourier_reps = 0
         args.mixed_steps = 0
+        args.graph_steps = 0
         args.no_cpu_baseline = True
     if args.fourier_reps > 0:
         out["fourier"] = fourier_sum(plan, sigma[0], args.fourier_reps)
         out["density"] = density_step(args.eps, args.fourier_reps)
+    if args.precision == "fp64" and args.graph_steps > 0 and not args.graph:
+        out["graph"] = graph_form(w, D, sigma, ms_step, args)
     if args.precision == "fp64" and args.mixed_steps > 0:
         del plan
         out["mixed"] = mixed_form(w, D, sigma, e_x, ms_step, args, "tiered")

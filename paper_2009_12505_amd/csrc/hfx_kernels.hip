@@ -896,7 +896,9 @@ __device__ __forceinline__ bool tile_has(const ItemLds &L, const uint8_t *mask, 
 //   out[(F,f)][(G,b)] = sum_{al,a} C_AF[al][a][f] T3_G[al][a][b]  -> summed over G into Sigma(F,B)
 // 128 x W blocks (W = 64 or 32, the plan's tile_r) in row-block-major order; a block whose tiles
 // hold no kept unit is skipped.
-template <int W, bool BF>
+// PR: the precision forms compiled in (0: FP64 only; 1: FP64 and FP32; 2: FP64, FP32 and
+// split-BF16x3), so that a plan's kernel carries no code, and no registers, for forms it never runs.
+template <int W, int PR>
 __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
                              const uint8_t *row2i, const short *col2jj, double *As, double *Bs, double *acc3,
                              int ld3, const float *ub, int tier, float tau, float tau_bf) {
@@ -938,8 +940,8 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
       const unsigned act_all = L.blk_act;
       if (!act_all) continue;
       const float bub = __uint_as_float(L.blk_ub);
-      const bool bf = BF && tier == 3 && bub <= tau_bf;
-      const bool fp32 = bf || tier == 2 || (tiered && bub <= tau);
+      const bool bf = PR == 2 && tier == 3 && bub <= tau_bf;
+      const bool fp32 = PR >= 1 && (bf || tier == 2 || (tiered && bub <= tau));
       const unsigned act = (act_all >> (NCT * wave)) & ((1u << NCT) - 1u);
       const int c = cb * W + (tid & (W - 1));
       const bool cok = c < L.NR;
@@ -957,7 +959,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
         }
       }
       d4 acc[NCT];
-      if constexpr (BF) {
+      if constexpr (PR == 2) {
         if (bf) {
           f4 a32[NCT];
 #pragma unroll
@@ -1130,6 +1132,7 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const shor
 // Per 64-column block: the masked D panel over the F's with a kept unit in the block is staged
 // once in the workgroup's scratch, P (all rows x 64) is formed by 128 x 64 block products with
 // C read from the per-block transposed copy, then contracted with Y on the matrix cores.
+template <int PR>
 __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
                              const short *col2jj, double *As, double *Bs, double *wg, int rows_cap,
                              long long *kaddr /* LDS [rows_cap] */, const float *ub, int tier, float tau) {
@@ -1178,7 +1181,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
     }
     __syncthreads();
     if (!L.blk_act) continue;
-    const bool fp32 = tier == 2 || ((tier == 1 || tier == 3) && __uint_as_float(L.blk_ub) <= tau);
+    const bool fp32 = PR >= 1 && (tier == 2 || ((tier == 1 || tier == 3) && __uint_as_float(L.blk_ub) <= tau));
     if (tid == 0) {
       int kc = 0, m = 0;
       for (int i = 0; i < nF; ++i)
@@ -1288,7 +1291,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
 }
 
 // ---------------------------------------------------------------------------------------------
-template <int W, bool BF>
+template <int W, int PR>
 __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
   __shared__ ItemLds L;
   extern __shared__ double dyn[];
@@ -1521,11 +1524,11 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     __syncthreads();
     tick(2);
     if (L.nGa > 0) {
-      phase_gemm_r<W, BF>(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
+      phase_gemm_r<W, PR>(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
                    kp.tier, kp.tau, kp.tau_bf);
       __syncthreads();
       tick(3);
-      phase_gemm_l(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr, ub, kp.tier,
+      phase_gemm_l<PR>(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr, ub, kp.tier,
                    kp.tau);
     }
     __syncthreads();
@@ -1837,8 +1840,8 @@ hipError_t launch_to_f32(const double *src, float *dst, long long n, hipStream_t
 
 hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3) {
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
-  const void *fns[] = {(const void *)k_main<64, false>, (const void *)k_main<32, false>,
-                       (const void *)k_main<64, true>, (const void *)k_main<32, true>};
+  const void *fns[] = {(const void *)k_main<64, 0>, (const void *)k_main<32, 0>, (const void *)k_main<64, 1>,
+                       (const void *)k_main<32, 1>, (const void *)k_main<64, 2>, (const void *)k_main<32, 2>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
@@ -1855,15 +1858,17 @@ hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap
     hipError_t e = main_set_lds(rows_cap, cols_cap, ld3);
     if (e != hipSuccess) return e;
   }
-  const bool bf = tier == 3;
-  if (tile_r == 32 && bf)
-    hipLaunchKernelGGL((k_main<32, true>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
-  else if (tile_r == 32)
-    hipLaunchKernelGGL((k_main<32, false>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
-  else if (bf)
-    hipLaunchKernelGGL((k_main<64, true>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
-  else
-    hipLaunchKernelGGL((k_main<64, false>), dim3(n_slots), dim3(NT), dyn, s, P, kp);
+  const int pr = tier == 0 ? 0 : tier == 3 ? 2 : 1;
+  const dim3 g(n_slots), b(NT);
+  if (tile_r == 32) {
+    if (pr == 0) hipLaunchKernelGGL((k_main<32, 0>), g, b, dyn, s, P, kp);
+    if (pr == 1) hipLaunchKernelGGL((k_main<32, 1>), g, b, dyn, s, P, kp);
+    if (pr == 2) hipLaunchKernelGGL((k_main<32, 2>), g, b, dyn, s, P, kp);
+  } else {
+    if (pr == 0) hipLaunchKernelGGL((k_main<64, 0>), g, b, dyn, s, P, kp);
+    if (pr == 1) hipLaunchKernelGGL((k_main<64, 1>), g, b, dyn, s, P, kp);
+    if (pr == 2) hipLaunchKernelGGL((k_main<64, 2>), g, b, dyn, s, P, kp);
+  }
   return hipGetLastError();
 }
 

@@ -1252,7 +1252,7 @@ hfx_status hfx_build(hfx_plan *p, const hfx_blocks *D, double *const *sigma, hfx
     stats->mfma_flops_bf16 = 16384.0 * mRbf;
     stats->tile_r = p->tile_r;
     stats->tier_tau = p->tier ? p->tau64 : 0.0;
-    stats->tier_tau_bf = p->tau_bf;
+    stats->tier_tau_bf = p->tier == 3 ? p->tau_bf : 0.0;
     float ms0 = 0, ms1 = 0;
     HIPCHK(p, hipEventElapsedTime(&ms0, p->ev0, p->ev2));
     HIPCHK(p, hipEventElapsedTime(&ms1, p->ev1, p->ev2));

@@ -72,3 +72,34 @@ def test_cfg3_eps1e6_tiered_vs_primitive():
     every Sigma block against the oracle's primitive-cell block of the same atom pair."""
     from paper_2009_12505_amd import PREC_TIERED
     _supercell_vs_primitive("cfg3", 1e-6, 1e-9, precision=PREC_TIERED, tier_tau=TAU)
+
+
+@pytest.mark.timeout(900)
+def test_cfg2_tiered_vs_primitive():
+    """The 64-atom cell (13 AO / 40 ABF, eps 1e-6) in the tiered form: every Sigma block against the
+    oracle's primitive-cell block, within the method's target."""
+    from paper_2009_12505_amd import PREC_TIERED
+    _supercell_vs_primitive("cfg2", 1e-6, 1e-9, precision=PREC_TIERED, tier_tau=TAU)
+
+
+@pytest.mark.timeout(900)
+def test_cfg4_tiered_batch_home_subset():
+    """The 48-cell batch of two species in one launch in the tiered form (one seeded home atom per
+    cell): three seeded cells against the oracle of that cell, within the method's target."""
+    from paper_2009_12505_amd import PREC_TIERED
+    log("case cfg4 tiered")
+    w = hs.make_workload("cfg4")
+    rng = np.random.default_rng(2009)
+    home_local = [int(rng.integers(c.n_atoms)) for c in w.cells]
+    offs = np.cumsum([0] + [c.n_atoms for c in w.cells])
+    home = [int(offs[k] + a) for k, a in enumerate(home_local)]
+    sig, e, st = gpu_build(w, home_subset=home, precision=PREC_TIERED, tier_tau=TAU)
+    log(f"cfg4 tiered: FP32 MFMA share {st['mfma_flops_fp32'] / max(sum(st['mfma_flops']), 1):.3f}")
+    assert st["mfma_flops_fp32"] > 0
+    for k in sorted(rng.choice(len(w.cells), size=3, replace=False).tolist()):
+        cell = w.cells[k]
+        ref = oracle.run(cell, w.C[k], w.V[k], w.D[k], w.thresholds, home=[home_local[k]], n_threads=16)
+        err = float(np.abs(sig[k] - ref.sigma).max())
+        de = abs(e[k] - oracle.energy(cell, w.D[k], ref.sigma))
+        log(f"cfg4 tiered cell {k} ({cell.n_atoms} atoms): max|dSigma| {err:.3e}, |dE_x| (one home atom) {de:.3e}")
+        assert err <= 1e-7 and de <= 1e-8
