@@ -30,6 +30,22 @@ namespace hfx {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Global-memory (address space 1) views of device buffers.  Through a generic pointer the
+// compiler emits flat loads and stores, which count against the LDS wait counter as well as the
+// vector-memory one: every wait for an LDS read then also waits for all global loads in flight, so
+// the prefetch of a block product's next chunk would not overlap the current chunk's MFMAs.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ gmem<T> *gptr(T *p) {
+  return (gmem<T> *)p;
+}
+template <class T>
+using smem = __attribute__((address_space(3))) T;  // LDS
+__device__ __forceinline__ void gatomic_add(gmem<double> *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int NT = 512;
 constexpr int NW = NT / 64;
 constexpr int MAXNB = 160;
@@ -132,8 +148,10 @@ struct KParams {
 
 // ---------------------------------------------------------------------------------------------
 // screen: CS-ERI + stage 1 on the F x G grid
-__device__ void phase_screen(const DevPlan &P, ItemLds &L, int *dfg, uint8_t *mask) {
+__device__ void phase_screen(const DevPlan &P, ItemLds &L, gmem<int> *dfg, gmem<uint8_t> *mask) {
   const int tid = threadIdx.x;
+  const gmem<const double> *gD = gptr(P.gD);
+  const gmem<const uint8_t> *keepD = gptr(P.keepD);
   const int nF = L.nF, nG = L.nG;
   const double eps = P.eps_mat, eps_eri = P.eps_eri;
   const bool use_eri = P.stages & kCsEri, use1 = P.stages & kCs1;
@@ -146,27 +164,27 @@ __device__ void phase_screen(const DevPlan &P, ItemLds &L, int *dfg, uint8_t *ma
       // D_FG is needed by term 1 (operand) and term 4 (target); skip the lookup when
       // neither can pass stage 1
       const bool may1 = !use1 || L.f_gA[i] * L.gV * L.g_gA[j] * L.gDmax > eps;
-      const bool may4 = L.okAB && (!use1 || L.f_gF[i] * L.gV * L.g_gF[j] * P.gD[L.dAB] > eps);
+      const bool may4 = L.okAB && (!use1 || L.f_gF[i] * L.gV * L.g_gF[j] * gD[L.dAB] > eps);
       if (may1 || may4) dFG = lookup_local(P, L.tbase, L.tn, L.f_loc[i], L.g_loc[j], r_sub(L.g_R[j], L.f_R[i]));
       bits = kCsOk;
       ++c_eri;
       // term 1: D_FG operand, target (A,B)
-      if (dFG >= 0 && P.keepD[dFG] && L.dAB >= 0) {
-        if (!use1 || L.f_gA[i] * L.gV * L.g_gA[j] * P.gD[dFG] > eps) bits |= kT1;
+      if (dFG >= 0 && keepD[dFG] && L.dAB >= 0) {
+        if (!use1 || L.f_gA[i] * L.gV * L.g_gA[j] * gD[dFG] > eps) bits |= kT1;
       }
       // term 2: D_FB operand, target (A,G)
       const int dFB = L.f_dFB[i];
-      if (dFB >= 0 && P.keepD[dFB] && L.g_dAG[j] >= 0) {
-        if (!use1 || L.f_gA[i] * L.gV * L.g_gF[j] * P.gD[dFB] > eps) bits |= kT2;
+      if (dFB >= 0 && keepD[dFB] && L.g_dAG[j] >= 0) {
+        if (!use1 || L.f_gA[i] * L.gV * L.g_gF[j] * gD[dFB] > eps) bits |= kT2;
       }
       // term 3: D_AG operand, target (F,B)
       const int dAG = L.g_dAG[j];
-      if (dAG >= 0 && P.keepD[dAG] && dFB >= 0) {
-        if (!use1 || L.f_gF[i] * L.gV * L.g_gA[j] * P.gD[dAG] > eps) bits |= kT3;
+      if (dAG >= 0 && keepD[dAG] && dFB >= 0) {
+        if (!use1 || L.f_gF[i] * L.gV * L.g_gA[j] * gD[dAG] > eps) bits |= kT3;
       }
       // term 4: D_AB operand, target (F,G)
       if (L.okAB && dFG >= 0) {
-        if (!use1 || L.f_gF[i] * L.gV * L.g_gF[j] * P.gD[L.dAB] > eps) bits |= kT4;
+        if (!use1 || L.f_gF[i] * L.gV * L.g_gF[j] * gD[L.dAB] > eps) bits |= kT4;
       }
       for (int t = 0; t < 4; ++t) c1[t] += (bits >> t) & 1;
       if (bits & 15) L.g_alive[j] = 1;
@@ -234,13 +252,21 @@ __device__ __forceinline__ d4 tile_mm_burst(int K, FA fa, FB fb, d4 acc) {
 // the Gram matrices N1[b] = Y_b^T Y_b and M2[g] = Y_g^T Y_g, and the slice norms of stages 2, 3.
 // Kept out of line: its load bursts need many registers, and inlined they would push the
 // register allocation of the block products past the budget of two waves per SIMD.
-__device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *slot, int jj, const double *Vsrc) {
+template <bool VL>
+__device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<double> *slot, int jj,
+                                        const smem<const double> *Vl, const gmem<const double> *Vg) {
   const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
   const int j = L.a_j[jj];
   const int PA = L.PA, PB = L.PB, na = L.na, nb = L.nb, ng = L.g_n[j];
   const int N = nb * ng;
-  const double *C = P.Cbuf + L.g_coff[j];
-  double *Y = slot + L.a_y[jj];
+  const gmem<const double> *C = gptr(P.Cbuf) + L.g_coff[j];
+  gmem<double> *Y = slot + L.a_y[jj];
+  auto vat = [&](int q) -> double {
+    if constexpr (VL)
+      return Vl[q];
+    else
+      return Vg[q];
+  };
   unsigned long long nm = 0;
   // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]; four alpha tiles share each C fragment,
   // which is fetched 32 K at a time before its MFMAs
@@ -267,7 +293,7 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
           for (int u = 0; u < 4; ++u) {
             if (rg + u >= mt) break;
             const int row = ((rg + u) << 4) + l16;
-            const double a = (row < PA && k < PB) ? Vsrc[row * PB + k] : 0.0;
+            const double a = (row < PA && k < PB) ? vat(row * PB + k) : 0.0;
             acc[u] = mfma64(a, bv[s], acc[u]);
           }
         }
@@ -286,7 +312,7 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
   // T4[(al,a)][g] = sum_b D_AB[a][b] Y[al][b][g]: D_AB fragments once, two alphas' Y at a time
   double t4max = 0.0;
   if (L.okAB) {
-    double *T4 = slot + L.a_t4[jj];
+    gmem<double> *T4 = slot + L.a_t4[jj];
     for (int g0 = 0; g0 < ng; g0 += 16) {
       double sq = 0.0;  // sum over (al, a) of T4^2 for column g = g0 + l16 (this lane's rows)
       const int g = g0 + l16;
@@ -333,9 +359,9 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
   // T3[(al,a)][b] = sum_g D_AG[a][g] Y[al][b][g]: D_AG fragments once, two alphas' Y at a time
   double t3max = 0.0;
   const int dAG = L.g_dAG[j];
-  if (dAG >= 0 && P.keepD[dAG]) {
-    const double *DAG = P.Dbuf + L.g_dAGoff[j];
-    double *T3 = slot + L.a_t3[jj];
+  if (dAG >= 0 && gptr(P.keepD)[dAG]) {
+    const gmem<const double> *DAG = gptr(P.Dbuf) + L.g_dAGoff[j];
+    gmem<double> *T3 = slot + L.a_t3[jj];
     for (int b0 = 0; b0 < nb; b0 += 16) {
       double sq = 0.0;  // sum over (al, a) of T3^2 for column b = b0 + l16 (this lane's rows)
       const int b = b0 + l16;
@@ -380,7 +406,7 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
     }
   }
   // N1[b][g][g'] = sum_al Y[al][b][g] Y[al][b][g'];  Yb^2 = max_b trace N1[b]
-  double *N1 = slot + L.a_n1[jj];
+  gmem<double> *N1 = slot + L.a_n1[jj];
   double ybmax = 0.0;
   for (int b = 0; b < nb; ++b) {
     double tr = 0.0;
@@ -388,7 +414,7 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
       for (int h0 = 0; h0 < ng; h0 += 16) {
         d4 h = {0, 0, 0, 0};
         for (int k0 = 0; k0 < PA; k0 += 32) {
-          const double *Yk = Y + (long long)k0 * N + b * ng;
+          const gmem<const double> *Yk = Y + (long long)k0 * N + b * ng;
           const int K = min(32, PA - k0);
           h = tile_mm_burst(
               K, [&](int r, int k) { return g0 + r < ng ? Yk[(long long)k * N + g0 + r] : 0.0; },
@@ -405,7 +431,7 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
     ybmax = fmax(ybmax, wave_sum(tr));
   }
   // M2[g][b][b'] = sum_al Y[al][b][g] Y[al][b'][g];  Yg^2 = max_g trace M2[g]
-  double *M2 = slot + L.a_m2[jj];
+  gmem<double> *M2 = slot + L.a_m2[jj];
   double ygmax = 0.0;
   for (int g = 0; g < ng; ++g) {
     double tr = 0.0;
@@ -413,7 +439,7 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
       for (int c0 = 0; c0 < nb; c0 += 16) {
         d4 h = {0, 0, 0, 0};
         for (int k0 = 0; k0 < PA; k0 += 32) {
-          const double *Yk = Y + (long long)k0 * N + g;
+          const gmem<const double> *Yk = Y + (long long)k0 * N + g;
           const int K = min(32, PA - k0);
           h = tile_mm_burst(
               K, [&](int r, int k) { return b0 + r < nb ? Yk[(long long)k * N + (b0 + r) * ng] : 0.0; },
@@ -442,8 +468,10 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, double *sl
 
 // ---------------------------------------------------------------------------------------------
 // masks: stages 2 and 3 for the stage-1 survivors of alive G's
-__device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, uint8_t *mask, double *E2,
-                            double *wreg, float *ub) {
+__device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, const gmem<int> *dfg, gmem<uint8_t> *mask,
+                            gmem<double> *E2, gmem<double> *wreg, gmem<float> *ub) {
+  const gmem<const double> *gD = gptr(P.gD), *Dbuf = gptr(P.Dbuf);
+  const gmem<const long long> *d_off = gptr(P.d_off);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int nb = L.nb, nF = L.nF, nGa = L.nGa, nG = L.nG;
   const double eps = P.eps_mat;
@@ -454,11 +482,11 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
   double cb = 0.0;
   // E2_i = D_FB^T D_FB  [b][b']  (one wave per F)
   for (int i = wave; i < nF; i += NW) {
-    double *E = E2 + (long long)i * nb * nb;
+    gmem<double> *E = E2 + (long long)i * nb * nb;
     const int dFB = L.f_dFB[i];
     const int nf = L.f_n[i];
     if (dFB < 0) continue;
-    const double *D = P.Dbuf + L.f_dFBoff[i];
+    const gmem<const double> *D = Dbuf + L.f_dFBoff[i];
     for (int b0 = 0; b0 < nb; b0 += 16)
       for (int c0 = 0; c0 < nb; c0 += 16) {
         const d4 h = tile_mm(
@@ -482,7 +510,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       continue;
     }
     if (bits & kT1) {
-      const double b = L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]];
+      const double b = L.f_gA[i] * L.a_Yb[jj] * gD[dfg[q]];
       if (!use2 || b > eps) {
         ++c2[0];
         if (use3) {
@@ -496,7 +524,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       }
     }
     if (bits & kT2) {
-      const double b = L.f_gA[i] * L.a_Yg[jj] * P.gD[L.f_dFB[i]];
+      const double b = L.f_gA[i] * L.a_Yg[jj] * gD[L.f_dFB[i]];
       if (!use2 || b > eps) {
         ++c2[1];
         if (use3) {
@@ -510,7 +538,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       }
     }
     if (bits & kT3) {
-      double b = L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]];
+      double b = L.f_gF[i] * L.a_Yb[jj] * gD[L.g_dAG[j]];
       bool keep = !use2 || b > eps;
       if (keep) {
         ++c2[2];
@@ -526,7 +554,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       if (!keep) bits &= ~kT3;
     }
     if (bits & kT4) {
-      double b = L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB];
+      double b = L.f_gF[i] * L.a_Yg[jj] * gD[L.dAB];
       bool keep = !use2 || b > eps;
       if (keep) {
         ++c2[3];
@@ -545,10 +573,10 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
     if (ub) {
       // stage-2 bounds of the surviving units, per GEMM: [0] terms 1, 2; [1] terms 3, 4
       float bl = 0.0f, br = 0.0f;
-      if (bits & kT1) bl = fmaxf(bl, (float)(L.f_gA[i] * L.a_Yb[jj] * P.gD[dfg[q]]));
-      if (bits & kT2) bl = fmaxf(bl, (float)(L.f_gA[i] * L.a_Yg[jj] * P.gD[L.f_dFB[i]]));
-      if (bits & kT3) br = fmaxf(br, (float)(L.f_gF[i] * L.a_Yb[jj] * P.gD[L.g_dAG[j]]));
-      if (bits & kT4) br = fmaxf(br, (float)(L.f_gF[i] * L.a_Yg[jj] * P.gD[L.dAB]));
+      if (bits & kT1) bl = fmaxf(bl, (float)(L.f_gA[i] * L.a_Yb[jj] * gD[dfg[q]]));
+      if (bits & kT2) bl = fmaxf(bl, (float)(L.f_gA[i] * L.a_Yg[jj] * gD[L.f_dFB[i]]));
+      if (bits & kT3) br = fmaxf(br, (float)(L.f_gF[i] * L.a_Yb[jj] * gD[L.g_dAG[j]]));
+      if (bits & kT4) br = fmaxf(br, (float)(L.f_gF[i] * L.a_Yg[jj] * gD[L.dAB]));
       ub[2 * p] = bl;
       ub[2 * p + 1] = br;
     }
@@ -564,7 +592,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
       const int i = (it << 4) + l16;
       const bool pend = i < nF && (mask[i * nG + j] & kPend2);
       if (!__any(pend)) continue;
-      const double *M2 = slot + L.a_m2[jj];
+      const gmem<const double> *M2 = slot + L.a_m2[jj];
       const int K = nb * nb;
       double smax[4] = {0.0, 0.0, 0.0, 0.0};
       for (int g0 = 0; g0 < ng; g0 += 16) {
@@ -596,11 +624,11 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
     __syncthreads();
     // term 1, stage 3: ||T1[:,:,b]||^2 = <D_FG^T D_FG, N1_G[b]>; per G, 16 pending F's at a time:
     // E1_F = D_FG^T D_FG into the wave's scratch, then one 16-F x 16-b tile over K = ng*ng
-    double *E1 = wreg;  // [16][MAXN*MAXN]
+    gmem<double> *E1 = wreg;  // [16][MAXN*MAXN]
     for (int jj = wave; jj < nGa; jj += NW) {
       const int j = L.a_j[jj], ng = L.g_n[j];
       const int K = ng * ng;
-      const double *N1 = slot + L.a_n1[jj];
+      const gmem<const double> *N1 = slot + L.a_n1[jj];
       int ib = 0;
       for (;;) {
         // next batch of up to 16 pending F's
@@ -620,7 +648,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, double *slot, const in
         if (nbat == 0) break;
         for (int r = 0; r < nbat; ++r) {
           const int i = fl[r], nf = L.f_n[i];
-          const double *D = P.Dbuf + P.d_off[dfg[i * nG + j]];
+          const gmem<const double> *D = Dbuf + d_off[dfg[i * nG + j]];
           for (int g0 = 0; g0 < ng; g0 += 16)
             for (int h0 = 0; h0 < ng; h0 += 16) {
               const d4 h = tile_mm(
@@ -676,116 +704,149 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Workgroup block product: a 128-row x W-column output block (W = 64 or 32), K streamed through
-// two LDS stages in chunks of 16.  Each thread fetches four A elements (row tid&127) and W/32 B
-// elements (column tid%W) of the next chunk into registers while the MFMAs of the current chunk
-// run, then stores them into the other stage; wave w owns row tile w and the W/16 column tiles
-// (act: which of them to compute).
-// a_at(k) / b_at(k) return this thread's A / B element at k (0 outside the operands).
+// Workgroup block products: a 128-row x W-column output block (W = 64 or 32), K streamed through
+// two LDS stages in chunks.  Every thread fetches its share of a chunk's A and B elements into
+// registers two chunks ahead: the loads of chunk c+2 are issued before the MFMAs of chunk c, and
+// chunk c+1 (fetched one chunk earlier) is stored into the other stage after them, so a load has
+// two chunks of matrix-core work to land.  Wave w owns row tile w and the W/16 column tiles (act:
+// which of them to compute).
+//
+// a_at(k) / b_at(k) load this thread's A / B element at k from an in-bounds address for every
+// k < K; the element counts only if aok and k < Ka (A) or bok and k < K (B), else a zero is stored
+// in its place.  The test is applied when the element is stored into LDS, so that nothing waits
+// for a load before then, and fetches and stores run also past the end of K (clamped loads,
+// zeros stored): with no branch around them the compiler knows how many loads are in flight at
+// each store and waits only for the older chunk's.
 constexpr int BM = 128, BN = 64, BK = 16;  // BN: the widest block (stage sizes, terms 1 and 2)
 
+// x where ok, else +0 (bitwise: no branch, and no NaN or Inf of x survives)
+__device__ __forceinline__ double keep_if(double x, bool ok) {
+  return __longlong_as_double(__double_as_longlong(x) & -(long long)ok);
+}
+__device__ __forceinline__ float keep_if(float x, bool ok) { return __int_as_float(__float_as_int(x) & -(int)ok); }
+
+// The chunk pipeline shared by the block products.  R: one chunk's registers; fetch(k0, R&)
+// loads chunk k0, stash(st, k0, const R&) stores it into stage st, compute(st) runs the MFMAs of
+// stage st (only in a wave with work, active: the same in all its lanes).  Fetch, MFMAs and store
+// of a chunk are independent of each other and branch-free, one basic block, so that the
+// compiler can interleave the memory instructions with the MFMAs.  Chunk pairs, then an odd last
+// chunk: no exit from the middle of the loop body, whose edge back to the loop head would make
+// the compiler wait there for the first chunk's loads.
+template <int CK, class R, class Fetch, class Stash, class Compute>
+__device__ __forceinline__ void chunk_pipeline(int K, bool active, Fetch fetch, Stash stash, Compute compute) {
+  R r0, r1;
+  auto step = [&](int k0, int st, R &rf, const R &rs) {
+    if (active) {
+      fetch(k0 + 2 * CK, rf);
+      compute(st);
+      stash(st ^ 1, k0 + CK, rs);
+    } else {
+      fetch(k0 + 2 * CK, rf);
+      stash(st ^ 1, k0 + CK, rs);
+    }
+    __syncthreads();
+  };
+  __syncthreads();  // the previous user of the stages is done
+  fetch(0, r0);
+  stash(0, 0, r0);
+  fetch(CK, r1);
+  __syncthreads();
+  const int nch = (K + CK - 1) / CK;
+  int c = 0;
+  for (; c + 1 < nch; c += 2) {
+    step(c * CK, 0, r0, r1);
+    step((c + 1) * CK, 1, r1, r0);
+  }
+  if (c < nch) step(c * CK, 0, r0, r1);
+}
+
+// FP64 (v_mfma_f64_16x16x4f64), BK = 16 K per chunk: four A elements (row tid&127) and W/32 B
+// elements (column tid%W) per thread; per K step a wave reads its A fragment and all W/16 B
+// fragments from LDS before the step's MFMAs.
 template <int W, class AAt, class BAt>
-__device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, unsigned act, double *As, double *Bs,
-                                            d4 (&acc)[W / 16]) {
-  // As, Bs: two stages each ([2][BK][BM], [2][BK][W]); one barrier per chunk
+__device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, bool aok, int Ka, bool bok, unsigned act,
+                                            double *As, double *Bs, d4 (&acc)[W / 16]) {
+  // As, Bs: two stages each ([2][BK][BM], [2][BK][W])
   constexpr int NV = W / 16, RS = NT / W, NBF = BK / RS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int ar = tid & (BM - 1), akq = (tid >> 7) << 2;
   const int bc = tid & (W - 1), bk = tid / W;
-  double ra[4], rb[NBF];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0;
-#pragma unroll
-    for (int q = 0; q < NBF; ++q) rb[q] = k0 + bk + q * RS < K ? b_at(k0 + bk + q * RS) : 0.0;
+  const unsigned actw = __builtin_amdgcn_readfirstlane(act);  // the same in every lane of the wave
+  struct Regs {
+    double a[4], b[NBF];
   };
-  auto stash = [&](int st) {
-    double *a = As + st * BK * BM, *b = Bs + st * BK * W;
+  chunk_pipeline<BK, Regs>(
+      K, true,
+      [&](int k0, Regs &r) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = ra[s];
+        for (int s = 0; s < 4; ++s) r.a[s] = a_at(min(k0 + akq + s, K - 1));
 #pragma unroll
-    for (int q = 0; q < NBF; ++q) b[(bk + q * RS) * W + bc] = rb[q];
-  };
-  __syncthreads();  // the previous user of the stages is done
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  int st = 0;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const bool more = k0 + BK < K;
-    if (more) fetch(k0 + BK);
-    if (act) {
-      const double *a = As + st * BK * BM, *b = Bs + st * BK * W;
-#pragma unroll 2
-      for (int s = 0; s < BK / 4; ++s) {
-        const int kr = 4 * s + kk;
-        const double av = a[kr * BM + wave * 16 + l16];
+        for (int q = 0; q < NBF; ++q) r.b[q] = b_at(min(k0 + bk + q * RS, K - 1));
+      },
+      [&](int st, int k0, const Regs &r) {
+        double *a = As + st * BK * BM, *b = Bs + st * BK * W;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          if (act & (1u << v)) acc[v] = mfma64(av, b[kr * W + v * 16 + l16], acc[v]);
-      }
-    }
-    if (more) stash(st ^ 1);
-    __syncthreads();
-    st ^= 1;
-  }
+        for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = keep_if(r.a[s], aok & (k0 + akq + s < Ka));
+#pragma unroll
+        for (int q = 0; q < NBF; ++q) b[(bk + q * RS) * W + bc] = keep_if(r.b[q], bok & (k0 + bk + q * RS < K));
+      },
+      [&](int st) {  // every tile of an active wave: a branch per tile would split the block
+        const double *a = As + st * BK * BM + wave * 16 + l16, *b = Bs + st * BK * W + l16;
+#pragma unroll
+        for (int s = 0; s < BK / 4; ++s) {
+          const int kr = 4 * s + kk;
+          const double av = a[kr * BM];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] = mfma64(av, b[kr * W + v * 16], acc[v]);
+        }
+      });
 }
 
-// The same block product on the FP32 matrix cores (v_mfma_f32_16x16x4f32), BKF K per chunk.
-// Thread tid fetches BKF/4 A elements (row tid&127, k rows (BKF/4)*(tid>>7)..) and BKF/8 B
-// elements (column tid&63, k rows tid>>6 + 8q) per chunk.  B arrives in FP64 (T3/T4, the
-// D panel) and is rounded only when it is stored into the stage: rounded at the fetch, the
-// conversion makes the wave wait for the load there, and the next chunk's loads no longer
-// overlap the current chunk's MFMAs.  (32-K FP32 chunks fit the same LDS; measured no faster
-// and they spill more registers.)
+// FP32 (v_mfma_f32_16x16x4f32), BKF K per chunk: BKF/4 A elements (row tid&127, k rows
+// (BKF/4)*(tid>>7)..) and BKF/8 B elements (column tid&63, k rows tid>>6 + 8q) per thread.  B
+// arrives in FP64 (T3/T4, the D panel) and is rounded when it is stored into the stage.  (32-K
+// FP32 chunks fit the same LDS; measured no faster and they spill more registers.)
 constexpr int BKF = 16;
 static_assert(BKF * (BM + BN) * 4 <= BK * (BM + BN) * 8, "FP32 stages reuse the FP64 stage buffers");
 
 template <int W, class AAt, class BAt>
-__device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, unsigned act, float *As, float *Bs,
-                                              f4 (&acc)[W / 16]) {
+__device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, bool aok, int Ka, bool bok, unsigned act,
+                                              float *As, float *Bs, f4 (&acc)[W / 16]) {
   constexpr int NV = W / 16, RS = NT / W, NA = BKF / 4, NB = BKF / RS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int ar = tid & (BM - 1), akq = (tid >> 7) * NA;
   const int bc = tid & (W - 1), bk = tid / W;
-  float ra[NA];
-  double rb[NB];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int s = 0; s < NA; ++s) ra[s] = (k0 + akq + s < K) ? a_at(k0 + akq + s) : 0.0f;
-#pragma unroll
-    for (int q = 0; q < NB; ++q) rb[q] = k0 + bk + RS * q < K ? b_at(k0 + bk + RS * q) : 0.0;
+  const unsigned actw = __builtin_amdgcn_readfirstlane(act);
+  struct Regs {
+    float a[NA];
+    double b[NB];
   };
-  auto stash = [&](int st) {
-    float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
+  chunk_pipeline<BKF, Regs>(
+      K, actw != 0,
+      [&](int k0, Regs &r) {
 #pragma unroll
-    for (int s = 0; s < NA; ++s) a[(akq + s) * BM + ar] = ra[s];
+        for (int s = 0; s < NA; ++s) r.a[s] = a_at(min(k0 + akq + s, K - 1));
 #pragma unroll
-    for (int q = 0; q < NB; ++q) b[(bk + RS * q) * W + bc] = (float)rb[q];
-  };
-  __syncthreads();  // the previous user of the stages is done
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  int st = 0;
-  for (int k0 = 0; k0 < K; k0 += BKF) {
-    const bool more = k0 + BKF < K;
-    if (more) fetch(k0 + BKF);
-    if (act) {
-      const float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
-#pragma unroll 2
-      for (int s = 0; s < BKF / 4; ++s) {
-        const int kr = 4 * s + kk;
-        const float av = a[kr * BM + wave * 16 + l16];
+        for (int q = 0; q < NB; ++q) r.b[q] = b_at(min(k0 + bk + RS * q, K - 1));
+      },
+      [&](int st, int k0, const Regs &r) {
+        float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          if (act & (1u << v)) acc[v] = mfma32(av, b[kr * W + v * 16 + l16], acc[v]);
-      }
-    }
-    if (more) stash(st ^ 1);
-    __syncthreads();
-    st ^= 1;
-  }
+        for (int s = 0; s < NA; ++s) a[(akq + s) * BM + ar] = keep_if(r.a[s], aok & (k0 + akq + s < Ka));
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          b[(bk + RS * q) * W + bc] = keep_if((float)r.b[q], bok & (k0 + bk + RS * q < K));
+      },
+      [&](int st) {  // every tile of an active wave
+        const float *a = As + st * BKF * BM + wave * 16 + l16, *b = Bs + st * BKF * W + l16;
+#pragma unroll
+        for (int s = 0; s < BKF / 4; ++s) {
+          const int kr = 4 * s + kk;
+          const float av = a[kr * BM];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] = mfma32(av, b[kr * W + v * 16], acc[v]);
+        }
+      });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -807,66 +868,62 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 template <int W, class AAt, class BAt>
-__device__ __forceinline__ void wg_block_mm_bf3(int K, AAt a_at, BAt b_at, unsigned act, uint16_t *As, uint16_t *Bs,
-                                                f4 (&acc)[W / 16]) {
+__device__ __forceinline__ void wg_block_mm_bf3(int K, AAt a_at, BAt b_at, bool aok, int Ka, bool bok, unsigned act,
+                                                uint16_t *As, uint16_t *Bs, f4 (&acc)[W / 16]) {
   constexpr int NV = W / 16, KB = BKB * W / NT;  // B elements per thread and chunk (4 or 2)
   constexpr int ASZ = 2 * BM * BKB, BSZ = 2 * W * BKB;  // one stage: hi block then lo block
   static_assert(2 * ASZ * 2 <= 2 * BK * BM * 8 && 2 * BSZ * 2 <= 2 * BK * BN * 8, "BF16 stages fit the FP64 ones");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kg = lane >> 4, l16 = lane & 15;
   const int ar = tid & (BM - 1), ako = (tid >> 7) * 8;
   const int bc = tid & (W - 1), bko = (tid / W) * KB;
-  float ra[8], rb[KB];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int s = 0; s < 8; ++s) ra[s] = (k0 + ako + s < K) ? a_at(k0 + ako + s) : 0.0f;
-#pragma unroll
-    for (int q = 0; q < KB; ++q) rb[q] = (k0 + bko + q < K) ? (float)b_at(k0 + bko + q) : 0.0f;
+  const unsigned actw = __builtin_amdgcn_readfirstlane(act);
+  struct Regs {
+    float a[8];
+    double b[KB];
   };
-  auto stash = [&](int st) {
-    uint16_t *a = As + st * ASZ, *b = Bs + st * BSZ;
+  chunk_pipeline<BKB, Regs>(
+      K, actw != 0,
+      [&](int k0, Regs &r) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const uint16_t h = bf16_rne(ra[s]);
-      a[ar * BKB + ako + s] = h;
-      a[BM * BKB + ar * BKB + ako + s] = bf16_rne(ra[s] - bf16_val(h));
-    }
+        for (int s = 0; s < 8; ++s) r.a[s] = a_at(min(k0 + ako + s, K - 1));
 #pragma unroll
-    for (int q = 0; q < KB; ++q) {
-      const uint16_t h = bf16_rne(rb[q]);
-      b[bc * BKB + bko + q] = h;
-      b[W * BKB + bc * BKB + bko + q] = bf16_rne(rb[q] - bf16_val(h));
-    }
-  };
-  __syncthreads();  // the previous user of the stages is done
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  int st = 0;
-  for (int k0 = 0; k0 < K; k0 += BKB) {
-    const bool more = k0 + BKB < K;
-    if (more) fetch(k0 + BKB);
-    if (act) {
-      const uint16_t *a = As + st * ASZ, *b = Bs + st * BSZ;
-      const bf8 ahi = *reinterpret_cast<const bf8 *>(a + (wave * 16 + l16) * BKB + kg * 8);
-      const bf8 alo = *reinterpret_cast<const bf8 *>(a + BM * BKB + (wave * 16 + l16) * BKB + kg * 8);
+        for (int q = 0; q < KB; ++q) r.b[q] = b_at(min(k0 + bko + q, K - 1));
+      },
+      [&](int st, int k0, const Regs &r) {
+        uint16_t *a = As + st * ASZ, *b = Bs + st * BSZ;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {  // every tile of an active wave (see the FP32 form)
-        const bf8 bhi = *reinterpret_cast<const bf8 *>(b + (v * 16 + l16) * BKB + kg * 8);
-        const bf8 blo = *reinterpret_cast<const bf8 *>(b + W * BKB + (v * 16 + l16) * BKB + kg * 8);
-        acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[v], 0, 0, 0);
-        acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[v], 0, 0, 0);
-        acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[v], 0, 0, 0);
-      }
-    }
-    if (more) stash(st ^ 1);
-    __syncthreads();
-    st ^= 1;
-  }
+        for (int s = 0; s < 8; ++s) {
+          const float x = keep_if(r.a[s], aok & (k0 + ako + s < Ka));
+          const uint16_t h = bf16_rne(x);
+          a[ar * BKB + ako + s] = h;
+          a[BM * BKB + ar * BKB + ako + s] = bf16_rne(x - bf16_val(h));
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+          const float x = keep_if((float)r.b[q], bok & (k0 + bko + q < K));
+          const uint16_t h = bf16_rne(x);
+          b[bc * BKB + bko + q] = h;
+          b[W * BKB + bc * BKB + bko + q] = bf16_rne(x - bf16_val(h));
+        }
+      },
+      [&](int st) {
+        const uint16_t *a = As + st * ASZ, *b = Bs + st * BSZ;
+        const bf8 ahi = *reinterpret_cast<const bf8 *>(a + (wave * 16 + l16) * BKB + kg * 8);
+        const bf8 alo = *reinterpret_cast<const bf8 *>(a + BM * BKB + (wave * 16 + l16) * BKB + kg * 8);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {  // every tile of an active wave: per-tile tests cost registers
+          const bf8 bhi = *reinterpret_cast<const bf8 *>(b + (v * 16 + l16) * BKB + kg * 8);
+          const bf8 blo = *reinterpret_cast<const bf8 *>(b + W * BKB + (v * 16 + l16) * BKB + kg * 8);
+          acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[v], 0, 0, 0);
+          acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[v], 0, 0, 0);
+          acc[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[v], 0, 0, 0);
+        }
+      });
 }
 
 // largest recorded bound over the alive G's whose columns meet [c_lo, c_hi), for row F_i
-__device__ __forceinline__ float cols_ub(const ItemLds &L, const float *ub, const short *col2jj, int i, int c_lo,
-                                         int c_hi, int which) {
+__device__ __forceinline__ float cols_ub(const ItemLds &L, const gmem<const float> *ub, const short *col2jj, int i,
+                                         int c_lo, int c_hi, int which) {
   float m = 0.0f;
   if (c_lo >= c_hi) return m;
   const int jj0 = col2jj[c_lo], jj1 = col2jj[c_hi - 1];
@@ -876,8 +933,8 @@ __device__ __forceinline__ float cols_ub(const ItemLds &L, const float *ub, cons
 
 // which of the four 16-column tiles of [c_lo, c_lo+64) hold a half (g or b) of some alive G
 // whose bit for F_i is set: bits_g for the g-half, bits_b for the b-half
-__device__ __forceinline__ bool tile_has(const ItemLds &L, const uint8_t *mask, const short *col2jj, int i, int c_lo,
-                                         int c_hi, uint8_t bits_g, uint8_t bits_b) {
+__device__ __forceinline__ bool tile_has(const ItemLds &L, const gmem<const uint8_t> *mask, const short *col2jj, int i,
+                                         int c_lo, int c_hi, uint8_t bits_g, uint8_t bits_b) {
   if (c_lo >= c_hi) return false;
   const int jj0 = col2jj[c_lo], jj1 = col2jj[c_hi - 1];
   for (int jj = jj0; jj <= jj1; ++jj) {
@@ -899,9 +956,12 @@ __device__ __forceinline__ bool tile_has(const ItemLds &L, const uint8_t *mask, 
 // PR: the precision forms compiled in (0: FP64 only; 1: FP64 and FP32; 2: FP64, FP32 and
 // split-BF16x3), so that a plan's kernel carries no code, and no registers, for forms it never runs.
 template <int W, int PR>
-__device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
-                             const uint8_t *row2i, const short *col2jj, double *As, double *Bs, double *acc3,
-                             int ld3, const float *ub, int tier, float tau, float tau_bf) {
+__device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *slot, const gmem<int> *dfg,
+                             const gmem<uint8_t> *mask, const uint8_t *row2i, const short *col2jj, double *As,
+                             double *Bs, double *acc3, int ld3, const gmem<float> *ub, int tier, float tau,
+                             float tau_bf) {
+  gmem<double> *Sbuf = gptr(P.Sbuf);
+  const gmem<const long long> *d_off = gptr(P.d_off);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int K = L.PA * L.na, nb = L.nb;
   const bool tiered = tier == 1 || tier == 3;
@@ -916,8 +976,8 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
     const bool rok = r < L.MR;
     const int ia = rok ? row2i[r] : 0;
     const long long a_off = L.f_coff[ia] + (rok ? r - L.f_row0[ia] : 0);
-    const double *Ab = P.Cbuf + a_off;
-    const float *Ab32 = tier ? P.C32 + a_off : nullptr;
+    const gmem<const double> *Ab = gptr(P.Cbuf) + a_off;
+    const gmem<const float> *Ab32 = tier ? gptr(P.C32) + a_off : nullptr;
     const int As_ = L.f_n[ia];
     for (int cb = 0; cb < ncb; ++cb) {
       if (tid == 0) {
@@ -945,7 +1005,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
       const unsigned act = (act_all >> (NCT * wave)) & ((1u << NCT) - 1u);
       const int c = cb * W + (tid & (W - 1));
       const bool cok = c < L.NR;
-      const double *Bb = slot;
+      const gmem<const double> *Bb = slot;
       int Bstr = 0;
       if (cok) {
         const int jj = col2jj[c], j = L.a_j[jj];
@@ -965,8 +1025,8 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 #pragma unroll
           for (int v = 0; v < NCT; ++v) a32[v] = f4{0, 0, 0, 0};
           wg_block_mm_bf3<W>(
-              K, [&](int k) { return rok ? Ab32[(long long)k * As_] : 0.0f; },
-              [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, reinterpret_cast<uint16_t *>(As),
+              K, [&](int k) { return Ab32[(long long)k * As_]; }, [&](int k) { return Bb[(long long)k * Bstr]; },
+              rok, K, cok, act, reinterpret_cast<uint16_t *>(As),
               reinterpret_cast<uint16_t *>(Bs), a32);
           nmfmabf += (unsigned long long)(act ? 3 * NCT : 0) * ((K + BKB - 1) / BKB);
 #pragma unroll
@@ -981,10 +1041,10 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 #pragma unroll
         for (int v = 0; v < NCT; ++v) a32[v] = f4{0, 0, 0, 0};
         wg_block_mm32<W>(
-            K, [&](int k) { return rok ? Ab32[(long long)k * As_] : 0.0f; },
-            [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, reinterpret_cast<float *>(As),
+            K, [&](int k) { return Ab32[(long long)k * As_]; }, [&](int k) { return Bb[(long long)k * Bstr]; }, rok, K,
+            cok, act, reinterpret_cast<float *>(As),
             reinterpret_cast<float *>(Bs), a32);
-        nmfma32 += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
+        nmfma32 += (unsigned long long)(act ? NCT : 0) * ((K + 3) >> 2);
 #pragma unroll
         for (int v = 0; v < NCT; ++v)
 #pragma unroll
@@ -993,9 +1053,9 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 #pragma unroll
         for (int v = 0; v < NCT; ++v) acc[v] = d4{0, 0, 0, 0};
         wg_block_mm<W>(
-            K, [&](int k) { return rok ? Ab[(long long)k * As_] : 0.0; },
-            [&](int k) { return cok ? Bb[(long long)k * Bstr] : 0.0; }, act, As, Bs, acc);
-        nmfma += (unsigned long long)__builtin_popcount(act) * ((K + 3) >> 2);
+            K, [&](int k) { return Ab[(long long)k * As_]; }, [&](int k) { return Bb[(long long)k * Bstr]; }, rok, K,
+            cok, act, As, Bs, acc);
+        nmfma += (unsigned long long)(act ? NCT : 0) * ((K + 3) >> 2);
       }
       // epilogue of this wave's tiles
 #pragma unroll
@@ -1013,7 +1073,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
           const uint8_t bits = mask[i * L.nG + j];
           const double w = unit_weight(L, i, j);
           if (cc < ng) {
-            if (bits & kT4) atomicAdd(P.Sbuf + P.d_off[dfg[i * L.nG + j]] + f * ng + cc, -w * acc[v][e]);
+            if (bits & kT4) gatomic_add(Sbuf + d_off[dfg[i * L.nG + j]] + f * ng + cc, -w * acc[v][e]);
           } else if (bits & kT3) {
             atomicAdd(&acc3[rl * ld3 + (cc - ng)], -w * acc[v][e]);
             any3 = true;
@@ -1030,7 +1090,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
         const double v = acc3[rl * ld3 + b];
         if (v != 0.0) {
           const int i = row2i[rr], f = rr - L.f_row0[i];
-          atomicAdd(P.Sbuf + L.f_dFBoff[i] + f * nb + b, v);
+          gatomic_add(Sbuf + L.f_dFBoff[i] + f * nb + b, v);
         }
       }
     }
@@ -1046,9 +1106,11 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, double *slot, const i
 //   wi >= NW (term 2, G = jj0 + wi - NW):  Sigma(A,G)[a][g] -= sum_{al, c} P[(al,a)][c] Y_G[al][b(c)][g]
 // The operands of up to eight K steps are loaded before their MFMAs; kept out of line so that
 // its registers do not count against the block products.  Returns the MFMAs issued.
-__device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const short *col2jj, const double *Pb,
-                                                          const double *slot, double *Sbuf, int wi, int c0, int c1,
-                                                          int jj0, unsigned long long t2m, bool t1any) {
+__device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const smem<const short> *col2jj,
+                                                          const gmem<const double> *Pb,
+                                                          const gmem<const double> *slot, gmem<double> *Sbuf, int wi,
+                                                          int c0, int c1, int jj0, unsigned long long t2m,
+                                                          bool t1any) {
   const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
   const int PA = L.PA, na = L.na, nb = L.nb;
   unsigned long long nm = 0;
@@ -1094,8 +1156,8 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const shor
   const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
   const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
   const int bc0 = max(c0, gb), bc1 = min(c1, g1);
-  const double *Yj = slot + L.a_y[jj];
-  double *S = Sbuf + L.g_dAGoff[j];
+  const gmem<const double> *Yj = slot + L.a_y[jj];
+  gmem<double> *S = Sbuf + L.g_dAGoff[j];
   for (int a0 = 0; a0 < na; a0 += 16)
     for (int g0 = 0; g0 < ng; g0 += 16) {
       d4 h = {0, 0, 0, 0};
@@ -1117,7 +1179,7 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const shor
       }
       for (int e = 0; e < 4; ++e) {
         const int a = a0 + kk + 4 * e, g = g0 + l16;
-        if (a < na && g < ng && h[e] != 0.0) atomicAdd(S + a * ng + g, -h[e]);
+        if (a < na && g < ng && h[e] != 0.0) gatomic_add(S + a * ng + g, -h[e]);
       }
     }
   return nm;
@@ -1133,16 +1195,19 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const shor
 // once in the workgroup's scratch, P (all rows x 64) is formed by 128 x 64 block products with
 // C read from the per-block transposed copy, then contracted with Y on the matrix cores.
 template <int PR>
-__device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const int *dfg, const uint8_t *mask,
-                             const short *col2jj, double *As, double *Bs, double *wg, int rows_cap,
-                             long long *kaddr /* LDS [rows_cap] */, const float *ub, int tier, float tau) {
+__device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *slot, const gmem<int> *dfg,
+                             const gmem<uint8_t> *mask, const short *col2jj, double *As, double *Bs,
+                             gmem<double> *wg, int rows_cap, long long *kaddr /* LDS [rows_cap] */,
+                             const gmem<float> *ub, int tier, float tau) {
+  const gmem<const double> *Dbuf = gptr(P.Dbuf);
+  const gmem<const long long> *d_off = gptr(P.d_off);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int M = L.PA * L.na, nb = L.nb, nF = L.nF;
   const int ncb = (L.NR + BN - 1) / BN, nrb = (M + BM - 1) / BM;
-  double *panel = wg;                                   // [rows_cap][64]
-  double *Pb = panel + (long long)rows_cap * BN;        // [M][64]
-  const double *CT = P.CTbuf;
-  const float *CT32 = P.CT32;
+  gmem<double> *panel = wg;                             // [rows_cap][64]
+  gmem<double> *Pb = panel + (long long)rows_cap * BN;  // [M][64]
+  const gmem<const double> *CT = gptr(P.CTbuf);
+  const gmem<const float> *CT32 = gptr(P.CT32);
   unsigned long long nmfma = 0, nmfma32 = 0;
   for (int cb = 0; cb < ncb; ++cb) {
     const int c0 = cb * BN, c1 = min(c0 + BN, L.NR);
@@ -1219,9 +1284,9 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
           const uint8_t bits = mask[i * L.nG + j];
           const double w = unit_weight(L, i, j);
           if (cc < ng) {
-            if (bits & kT1) val = w * P.Dbuf[P.d_off[dfg[i * L.nG + j]] + f * ng + cc];
+            if (bits & kT1) val = w * Dbuf[d_off[dfg[i * L.nG + j]] + f * ng + cc];
           } else if (bits & kT2) {
-            val = w * P.Dbuf[L.f_dFBoff[i] + f * nb + (cc - ng)];
+            val = w * Dbuf[L.f_dFBoff[i] + f * nb + (cc - ng)];
           }
         }
       } else {
@@ -1236,6 +1301,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
     for (int rb = 0; rb < nrb; ++rb) {
       const int r = rb * BM + (tid & (BM - 1));
       const bool rok = r < M;
+      const int rc = rok ? r : 0;  // an in-bounds row for the loads of rows past M
       const int bcl = tid & (BN - 1);
       d4 acc[4];
       const unsigned act = (rb * BM + wave * 16 < M) ? colact : 0u;
@@ -1244,14 +1310,10 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
 #pragma unroll
         for (int v = 0; v < 4; ++v) a32[v] = f4{0, 0, 0, 0};
         wg_block_mm32<BN>(
-            Kc,
-            [&](int k) {
-              const long long ka = kaddr[k];
-              return (rok && ka >= 0) ? CT32[ka + r] : 0.0f;
-            },
-            [&](int k) { return panel[(long long)k * BN + bcl]; }, act, reinterpret_cast<float *>(As),
+            Kc, [&](int k) { return CT32[max(kaddr[k], 0ll) + rc]; }, [&](int k) { return panel[(long long)k * BN + bcl]; },
+            rok, kc, true, act, reinterpret_cast<float *>(As),
             reinterpret_cast<float *>(Bs), a32);
-        nmfma32 += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
+        nmfma32 += (unsigned long long)(act ? 4 : 0) * (Kc >> 2);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -1260,13 +1322,9 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
         wg_block_mm<BN>(
-            Kc,
-            [&](int k) {
-              const long long ka = kaddr[k];
-              return (rok && ka >= 0) ? CT[ka + r] : 0.0;
-            },
-            [&](int k) { return panel[(long long)k * BN + bcl]; }, act, As, Bs, acc);
-        nmfma += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
+            Kc, [&](int k) { return CT[max(kaddr[k], 0ll) + rc]; }, [&](int k) { return panel[(long long)k * BN + bcl]; },
+            rok, kc, true, act, As, Bs, acc);
+        nmfma += (unsigned long long)(act ? 4 : 0) * (Kc >> 2);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -1282,7 +1340,8 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, double *slot, const i
     {
       const int nwork = (L.t1any ? NW : 0) + (jj1 - jj0 + 1);
       for (int wi = wave; wi < nwork; wi += NW)
-        nmfma += ycontract_wave(L, col2jj, Pb, slot, P.Sbuf, wi, c0, c1, jj0, L.t2any, L.t1any != 0);
+        nmfma += ycontract_wave(L, (const smem<const short> *)col2jj, Pb, slot, gptr(P.Sbuf), wi, c0, c1, jj0, L.t2any,
+                                L.t1any != 0);
     }
     __syncthreads();
   }
@@ -1304,7 +1363,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
   const int dyn_doubles = 2 * BK * BM + 2 * BK * BN + NW * 16 * kp.ld3;
   __shared__ int s_item;
   const int tid = threadIdx.x;
-  double *slot = P.scratch + (long long)blockIdx.x * P.slot_doubles;
+  gmem<double> *slot = gptr(P.scratch) + (long long)blockIdx.x * P.slot_doubles;
   for (;;) {
     if (tid == 0) {
       // the next item of this workgroup's group (workgroup b runs on XCD b mod 8), else of the
@@ -1409,11 +1468,11 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       L.MR = r0;
     }
     // slot scratch: dfg (int) and mask (bytes) over nF*nG, then E2, then per-G buffers
-    int *dfg = reinterpret_cast<int *>(slot);
+    gmem<int> *dfg = reinterpret_cast<gmem<int> *>(slot);
     const int nFG = L.nF * L.nG;
-    uint8_t *mask = reinterpret_cast<uint8_t *>(slot + ((nFG + 1) >> 1));
-    double *E2 = slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3);
-    double *gbase_d = E2 + L.nF * L.nb * L.nb;
+    gmem<uint8_t> *mask = reinterpret_cast<gmem<uint8_t> *>(slot + ((nFG + 1) >> 1));
+    gmem<double> *E2 = slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3);
+    gmem<double> *gbase_d = E2 + L.nF * L.nb * L.nb;
     __syncthreads();
     long long tp = wall_clock64();
     auto tick = [&](int ph) {
@@ -1461,15 +1520,20 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     {
       // V_AB in LDS when it fits in the accumulator region (not in use in this phase)
       const bool vlds = L.PA * L.PB <= dyn_doubles;
-      const double *Vsrc = vlds ? As : P.Vbuf + L.voff;
+      const gmem<const double> *Vg = gptr(P.Vbuf) + L.voff;
       if (vlds)
-        for (int q = tid; q < L.PA * L.PB; q += NT) As[q] = P.Vbuf[L.voff + q];
+        for (int q = tid; q < L.PA * L.PB; q += NT) As[q] = Vg[q];
       __syncthreads();
-      for (int jj = tid >> 6; jj < L.nGa; jj += NW) gside_wave(P, L, slot, jj, Vsrc);
+      for (int jj = tid >> 6; jj < L.nGa; jj += NW) {
+        if (vlds)
+          gside_wave<true>(P, L, slot, jj, (const smem<const double> *)As, Vg);
+        else
+          gside_wave<false>(P, L, slot, jj, (const smem<const double> *)As, Vg);
+      }
       __syncthreads();
     }
     tick(1);
-    float *ub = (kp.tier == 1 || kp.tier == 3) ? reinterpret_cast<float *>(slot + kp.ub_off) : nullptr;
+    gmem<float> *ub = (kp.tier == 1 || kp.tier == 3) ? reinterpret_cast<gmem<float> *>(slot + kp.ub_off) : nullptr;
     phase_masks(P, L, slot, dfg, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
@@ -1538,7 +1602,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       for (int q = tid; q < L.na * L.nb; q += NT) {
         const int a = q / L.nb, b = q - a * L.nb;
         const double v = L.H1[a * MAXN + b];
-        if (v != 0.0) atomicAdd(P.Sbuf + P.d_off[L.dAB] + q, -v);
+        if (v != 0.0) gatomic_add(gptr(P.Sbuf) + P.d_off[L.dAB] + q, -v);
       }
     if (tid < kCntN && L.cnt[tid]) atomicAdd(&P.counters[tid], L.cnt[tid]);
     if (tid < 2 && L.flops[tid] != 0.0) atomicAdd(&P.flops[tid], L.flops[tid]);
