@@ -148,8 +148,10 @@ struct KParams {
 
 // ---------------------------------------------------------------------------------------------
 // screen: CS-ERI + stage 1 on the F x G grid
-__device__ void phase_screen(const DevPlan &P, ItemLds &L, gmem<int> *dfg, gmem<uint8_t> *mask) {
+__device__ void phase_screen(const DevPlan &P, ItemLds &L, gmem<int> *dfg, gmem<long long> *doff,
+                             gmem<uint8_t> *mask) {
   const int tid = threadIdx.x;
+  const gmem<const long long> *d_off = gptr(P.d_off);
   const gmem<const double> *gD = gptr(P.gD);
   const gmem<const uint8_t> *keepD = gptr(P.keepD);
   const int nF = L.nF, nG = L.nG;
@@ -190,6 +192,7 @@ __device__ void phase_screen(const DevPlan &P, ItemLds &L, gmem<int> *dfg, gmem<
       if (bits & 15) L.g_alive[j] = 1;
     }
     dfg[p] = dFG;
+    doff[p] = dFG >= 0 ? d_off[dFG] : 0;
     mask[p] = bits;
   }
   atomicAdd(&L.cnt[kCntCsEri], c_eri);
@@ -468,10 +471,10 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<doubl
 
 // ---------------------------------------------------------------------------------------------
 // masks: stages 2 and 3 for the stage-1 survivors of alive G's
-__device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, const gmem<int> *dfg, gmem<uint8_t> *mask,
-                            gmem<double> *E2, gmem<double> *wreg, gmem<float> *ub) {
+__device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, const gmem<int> *dfg,
+                            const gmem<long long> *doff, gmem<uint8_t> *mask, gmem<double> *E2, gmem<double> *wreg,
+                            gmem<float> *ub) {
   const gmem<const double> *gD = gptr(P.gD), *Dbuf = gptr(P.Dbuf);
-  const gmem<const long long> *d_off = gptr(P.d_off);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int nb = L.nb, nF = L.nF, nGa = L.nGa, nG = L.nG;
   const double eps = P.eps_mat;
@@ -648,7 +651,7 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, co
         if (nbat == 0) break;
         for (int r = 0; r < nbat; ++r) {
           const int i = fl[r], nf = L.f_n[i];
-          const gmem<const double> *D = Dbuf + d_off[dfg[i * nG + j]];
+          const gmem<const double> *D = Dbuf + doff[i * nG + j];
           for (int g0 = 0; g0 < ng; g0 += 16)
             for (int h0 = 0; h0 < ng; h0 += 16) {
               const d4 h = tile_mm(
@@ -956,12 +959,11 @@ __device__ __forceinline__ bool tile_has(const ItemLds &L, const gmem<const uint
 // PR: the precision forms compiled in (0: FP64 only; 1: FP64 and FP32; 2: FP64, FP32 and
 // split-BF16x3), so that a plan's kernel carries no code, and no registers, for forms it never runs.
 template <int W, int PR>
-__device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *slot, const gmem<int> *dfg,
+__device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *slot, const gmem<long long> *doff,
                              const gmem<uint8_t> *mask, const uint8_t *row2i, const short *col2jj, double *As,
                              double *Bs, double *acc3, int ld3, const gmem<float> *ub, int tier, float tau,
                              float tau_bf) {
   gmem<double> *Sbuf = gptr(P.Sbuf);
-  const gmem<const long long> *d_off = gptr(P.d_off);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int K = L.PA * L.na, nb = L.nb;
   const bool tiered = tier == 1 || tier == 3;
@@ -1073,7 +1075,7 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
           const uint8_t bits = mask[i * L.nG + j];
           const double w = unit_weight(L, i, j);
           if (cc < ng) {
-            if (bits & kT4) gatomic_add(Sbuf + d_off[dfg[i * L.nG + j]] + f * ng + cc, -w * acc[v][e]);
+            if (bits & kT4) gatomic_add(Sbuf + doff[i * L.nG + j] + f * ng + cc, -w * acc[v][e]);
           } else if (bits & kT3) {
             atomicAdd(&acc3[rl * ld3 + (cc - ng)], -w * acc[v][e]);
             any3 = true;
@@ -1195,12 +1197,11 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const smem
 // once in the workgroup's scratch, P (all rows x 64) is formed by 128 x 64 block products with
 // C read from the per-block transposed copy, then contracted with Y on the matrix cores.
 template <int PR>
-__device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *slot, const gmem<int> *dfg,
-                             const gmem<uint8_t> *mask, const short *col2jj, double *As, double *Bs,
+__device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *slot, const gmem<long long> *doff,
+                             const gmem<uint8_t> *mask, uint8_t *row2i, const short *col2jj, double *As, double *Bs,
                              gmem<double> *wg, int rows_cap, long long *kaddr /* LDS [rows_cap] */,
                              const gmem<float> *ub, int tier, float tau) {
   const gmem<const double> *Dbuf = gptr(P.Dbuf);
-  const gmem<const long long> *d_off = gptr(P.d_off);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
   const int M = L.PA * L.na, nb = L.nb, nF = L.nF;
   const int ncb = (L.NR + BN - 1) / BN, nrb = (M + BM - 1) / BM;
@@ -1261,36 +1262,42 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
       L.kc = kc;
     }
     __syncthreads();
-    const int kc = L.kc, Kc = (kc + BK - 1) / BK * BK;
+    const int kc = L.kc, Kc = (kc + BK - 1) / BK * BK, nsel = L.nsel, nj = jj1 - jj0 + 1;
+    // panel row -> member table (row2i is free once GEMM-R is done), and per (member, G of the
+    // block) the offsets of the two operand blocks, D_FG (term 1) and D_FB (term 2), -1 where the
+    // unit is not kept: in the A stage, free here, when they fit
+    long long *uoff = reinterpret_cast<long long *>(As);
+    const bool tab = nsel * nj * 2 <= 2 * BK * BM;
+    for (int m = tid >> 6; m < nsel; m += NW)
+      for (int f = lane; f < L.f_n[L.fsel[m]]; f += 64) row2i[L.fsrow[m] + f] = (uint8_t)m;
+    if (tab)
+      for (int q = tid; q < nsel * nj; q += NT) {
+        const int m = q / nj, i = L.fsel[m], j = L.a_j[jj0 + q - m * nj];
+        const uint8_t bits = mask[i * L.nG + j];
+        uoff[2 * q] = (bits & kT1) ? doff[i * L.nG + j] : -1;
+        uoff[2 * q + 1] = (bits & kT2) ? L.f_dFBoff[i] : -1;
+      }
+    __syncthreads();
     // stage the masked D panel and the C^T row addresses
     for (int e = tid; e < Kc * BN; e += NT) {
       const int k = e >> 6, cl = e & (BN - 1), c = c0 + cl;
       double val = 0.0;
-      long long ka = 0;
+      long long ka = -1;
       if (k < kc) {
-        int lo = 0, hi = L.nsel - 1;  // last member whose first panel row is <= k
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (L.fsrow[mid] <= k)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const int i = L.fsel[lo], f = k - L.fsrow[lo];
+        const int m = row2i[k], i = L.fsel[m], f = k - L.fsrow[m];
         ka = L.f_coff[i] + (long long)f * M;
         if (c < c1) {
           const int jj = col2jj[c], j = L.a_j[jj];
           const int cc = c - L.a_col0[jj], ng = L.g_n[j];
-          const uint8_t bits = mask[i * L.nG + j];
-          const double w = unit_weight(L, i, j);
-          if (cc < ng) {
-            if (bits & kT1) val = w * Dbuf[d_off[dfg[i * L.nG + j]] + f * ng + cc];
-          } else if (bits & kT2) {
-            val = w * Dbuf[L.f_dFBoff[i] + f * nb + (cc - ng)];
+          long long o;
+          if (tab) {
+            o = uoff[2 * (m * nj + jj - jj0) + (cc < ng ? 0 : 1)];
+          } else {
+            const uint8_t bits = mask[i * L.nG + j];
+            o = cc < ng ? ((bits & kT1) ? doff[i * L.nG + j] : -1) : ((bits & kT2) ? L.f_dFBoff[i] : -1);
           }
+          if (o >= 0) val = unit_weight(L, i, j) * Dbuf[o + (cc < ng ? f * ng + cc : f * nb + (cc - ng))];
         }
-      } else {
-        ka = -1;
       }
       panel[(long long)k * BN + cl] = val;
       if (cl == 0) kaddr[k] = ka;
@@ -1467,11 +1474,13 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       L.f_row0[L.nF] = r0;
       L.MR = r0;
     }
-    // slot scratch: dfg (int) and mask (bytes) over nF*nG, then E2, then per-G buffers
+    // slot scratch: dfg (int), mask (bytes) and doff (D / Sigma offset of D_FG) over nF*nG, then E2,
+    // then per-G buffers
     gmem<int> *dfg = reinterpret_cast<gmem<int> *>(slot);
     const int nFG = L.nF * L.nG;
     gmem<uint8_t> *mask = reinterpret_cast<gmem<uint8_t> *>(slot + ((nFG + 1) >> 1));
-    gmem<double> *E2 = slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3);
+    gmem<long long> *doff = reinterpret_cast<gmem<long long> *>(slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3));
+    gmem<double> *E2 = slot + ((nFG + 1) >> 1) + ((nFG + 7) >> 3) + nFG;
     gmem<double> *gbase_d = E2 + L.nF * L.nb * L.nb;
     __syncthreads();
     long long tp = wall_clock64();
@@ -1483,7 +1492,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
       }
     };
     tick(5);
-    phase_screen(P, L, dfg, mask);
+    phase_screen(P, L, dfg, doff, mask);
     __syncthreads();
     tick(0);
     // compact alive G and lay out their buffers
@@ -1534,7 +1543,7 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     }
     tick(1);
     gmem<float> *ub = (kp.tier == 1 || kp.tier == 3) ? reinterpret_cast<gmem<float> *>(slot + kp.ub_off) : nullptr;
-    phase_masks(P, L, slot, dfg, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
+    phase_masks(P, L, slot, dfg, doff, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
       int lo = 0, hi = L.nF - 1;
@@ -1588,11 +1597,11 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     __syncthreads();
     tick(2);
     if (L.nGa > 0) {
-      phase_gemm_r<W, PR>(P, L, slot, dfg, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
+      phase_gemm_r<W, PR>(P, L, slot, doff, mask, row2i, col2jj, As, Bs, acc3 + (tid >> 6) * 16 * kp.ld3, kp.ld3, ub,
                    kp.tier, kp.tau, kp.tau_bf);
       __syncthreads();
       tick(3);
-      phase_gemm_l<PR>(P, L, slot, dfg, mask, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr, ub, kp.tier,
+      phase_gemm_l<PR>(P, L, slot, doff, mask, row2i, col2jj, As, Bs, slot + kp.wg_off, kp.rows_cap, kaddr, ub, kp.tier,
                    kp.tau);
     }
     __syncthreads();

@@ -822,7 +822,7 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
   if (p->rows_cap > 255 * 64 || p->cols_cap > 16 * 64 * 8)
     return fail(HFX_ERR_UNSUPPORTED, "neighbour lists too long for the decode tables");
   const int64_t nfg = (int64_t)max_nbr * max_nbr;
-  p->wave_off = (nfg + 1) / 2 + (nfg + 7) / 8 + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
+  p->wave_off = (nfg + 1) / 2 + (nfg + 7) / 8 + nfg + (int64_t)max_nbr * max_n * max_n + gside_max + 64;
   p->wave_doubles = (16 * (int64_t)main_maxn() * main_maxn() + 64 + 31) / 32 * 32;
   p->wg_off = p->wave_off + (int64_t)main_nwaves() * p->wave_doubles;
   const int64_t wg_doubles = (int64_t)p->rows_cap * 64 + (int64_t)max_p * max_n * 64 + 64;
