@@ -118,8 +118,6 @@ struct ItemLds {
   double a_Yb[MAXNB], a_Yg[MAXNB], a_T3n[MAXNB], a_T4n[MAXNB];
   double H1[MAXN * MAXN];
   double DAB[MAXN * MAXN];
-  double DAG[MAXN * MAXN];
-  double sq[2 * MAXN];
   // GEMM block bookkeeping
   unsigned blk_act;
   unsigned blk_ub;  // largest stage-2 bound (float bits) of the kept units of the current block
@@ -1059,29 +1057,50 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
             cok, act, As, Bs, acc);
         nmfma += (unsigned long long)(act ? NCT : 0) * ((K + 3) >> 2);
       }
-      // epilogue of this wave's tiles
+      // epilogue of this wave's tiles: the (F,G) records of all its elements are loaded before
+      // the first atomic, so that the loads overlap one another
+      int ei[4], ef[4], vj[NCT], vc[NCT], vn[NCT];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = rb * BM + wave * 16 + (fp32 ? 4 * kk + e : kk + 4 * e);  // result row (MFMA form)
+        ei[e] = rr < L.MR ? row2i[rr] : -1;
+        ef[e] = ei[e] >= 0 ? rr - L.f_row0[ei[e]] : 0;
+      }
 #pragma unroll
       for (int v = 0; v < NCT; ++v) {
-        if (!(act & (1u << v))) continue;
         const int cc0 = cb * W + v * 16 + l16;
-        if (cc0 >= L.NR) continue;
-        const int jj = col2jj[cc0], j = L.a_j[jj];
-        const int cc = cc0 - L.a_col0[jj], ng = L.g_n[j];
+        const bool ok = (act & (1u << v)) && cc0 < L.NR;
+        const int jj = ok ? col2jj[cc0] : 0, j = L.a_j[jj];
+        vj[v] = ok ? j : -1;
+        vc[v] = cc0 - L.a_col0[jj];
+        vn[v] = L.g_n[j];
+      }
+      uint8_t ubits[NCT][4];
+      long long uoff[NCT][4];
+#pragma unroll
+      for (int v = 0; v < NCT; ++v)
+#pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int rl = fp32 ? 4 * kk + e : kk + 4 * e;  // result row of element e (MFMA form)
-          const int rr = rb * BM + wave * 16 + rl;
-          if (rr >= L.MR) continue;
-          const int i = row2i[rr], f = rr - L.f_row0[i];
-          const uint8_t bits = mask[i * L.nG + j];
+          const bool ok = vj[v] >= 0 && ei[e] >= 0;
+          const int q = ok ? ei[e] * L.nG + vj[v] : 0;
+          ubits[v][e] = ok ? mask[q] : 0;
+          uoff[v][e] = doff[q];
+        }
+#pragma unroll
+      for (int v = 0; v < NCT; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint8_t bits = ubits[v][e];
+          if (!(bits & (kT3 | kT4))) continue;
+          const int i = ei[e], j = vj[v], cc = vc[v], ng = vn[v];
           const double w = unit_weight(L, i, j);
           if (cc < ng) {
-            if (bits & kT4) gatomic_add(Sbuf + doff[i * L.nG + j] + f * ng + cc, -w * acc[v][e]);
+            if (bits & kT4) gatomic_add(Sbuf + uoff[v][e] + ef[e] * ng + cc, -w * acc[v][e]);
           } else if (bits & kT3) {
-            atomicAdd(&acc3[rl * ld3 + (cc - ng)], -w * acc[v][e]);
+            atomicAdd(&acc3[(fp32 ? 4 * kk + e : kk + 4 * e) * ld3 + (cc - ng)], -w * acc[v][e]);
             any3 = true;
           }
         }
-      }
     }
     // flush term 3 of this wave's 16 rows: Sigma(F,B)[f][b]
     if (__any(any3)) {
@@ -1105,9 +1124,12 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
 // ---------------------------------------------------------------------------------------------
 // One work item of the Y contraction of a GEMM-L column block [c0, c1), by one wave:
 //   wi < NW (term 1, alpha part wi):  H1[a][b] += sum_{al in part, c} P[(al,a)][c] Y_G(c)[al][b][g(c)]
-//   wi >= NW (term 2, G = jj0 + wi - NW):  Sigma(A,G)[a][g] -= sum_{al, c} P[(al,a)][c] Y_G[al][b(c)][g]
+//   wi >= NW (term 2, G = jj0 + (wi - NW) / kY2Parts, alpha part (wi - NW) % kY2Parts):
+//            Sigma(A,G)[a][g] -= sum_{al in part, c} P[(al,a)][c] Y_G[al][b(c)][g]
+// (term 2 is split over alpha like term 1, so that the eight waves share the work evenly)
 // The operands of up to eight K steps are loaded before their MFMAs; kept out of line so that
 // its registers do not count against the block products.  Returns the MFMAs issued.
+constexpr int kY2Parts = 4;
 __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const smem<const short> *col2jj,
                                                           const gmem<const double> *Pb,
                                                           const gmem<const double> *slot, gmem<double> *Sbuf, int wi,
@@ -1153,8 +1175,9 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const smem
       }
     return nm;
   }
-  const int q = wi - (t1any ? NW : 0);
+  const int q = (wi - (t1any ? NW : 0)) / kY2Parts, part = (wi - (t1any ? NW : 0)) % kY2Parts;
   if (!((t2m >> q) & 1ull)) return 0;
+  const int al0 = part * PA / kY2Parts, al1 = (part + 1) * PA / kY2Parts;
   const int jj = jj0 + q, j = L.a_j[jj], ng = L.g_n[j];
   const int gb = L.a_col0[jj] + ng, g1 = L.a_col0[jj + 1];
   const int bc0 = max(c0, gb), bc1 = min(c1, g1);
@@ -1163,7 +1186,7 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const smem
   for (int a0 = 0; a0 < na; a0 += 16)
     for (int g0 = 0; g0 < ng; g0 += 16) {
       d4 h = {0, 0, 0, 0};
-      for (int al = 0; al < PA; ++al) {
+      for (int al = al0; al < al1; ++al) {
         double av[8], bv[8];  // the b columns of this G in the block: at most 32
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -1345,7 +1368,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
     __syncthreads();
     // contractions with Y: work items (target, alpha part); target 0 = term 1, 1+q = term 2 of jj0+q
     {
-      const int nwork = (L.t1any ? NW : 0) + (jj1 - jj0 + 1);
+      const int nwork = (L.t1any ? NW : 0) + (jj1 - jj0 + 1) * kY2Parts;
       for (int wi = wave; wi < nwork; wi += NW)
         nmfma += ycontract_wave(L, (const smem<const short> *)col2jj, Pb, slot, gptr(P.Sbuf), wi, c0, c1, jj0, L.t2any,
                                 L.t1any != 0);
