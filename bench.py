@@ -299,6 +299,8 @@ def main():
                     help="run the autotuner on a subset of home atoms of the workload (fp64, tiered, bf16x3) "
                          "and append its choices to --tuning-db (default: the committed file), then exit")
     ap.add_argument("--tune-homes", type=int, default=32, help="home atoms of the tuning subset")
+    ap.add_argument("--tile-r", type=int, default=0, choices=[0, 32, 64, 128],
+                    help="column width of the terms-3/4 output blocks (0: the tuning file's choice, else 64)")
     ap.add_argument("--graph", action="store_true",
                     help="replay the build as one captured HIP graph (kernel time = whole graph)")
     ap.add_argument("--graph-steps", type=int, default=1,
@@ -353,7 +355,7 @@ def main():
     sched_kind = {"lpt": hfx.SCHED_LPT, "plan": hfx.SCHED_PLAN, "exact": hfx.SCHED_EXACT, "norm": hfx.SCHED_NORM,
                   "kmeans": hfx.SCHED_KMEANS}[args.scheduler]
     plan = Plan(w.cells, w.C, w.V, w.D, w.thresholds, precision=prec, tier_tau=args.tau, tier_tau_bf=args.tau_bf,
-                use_graph=args.graph, scheduler=sched_kind, tuning_db=args.tuning_db)
+                use_graph=args.graph, scheduler=sched_kind, tuning_db=args.tuning_db, tile_r=args.tile_r)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     progress(f"plan created in {t_plan:.1f}s")

@@ -163,11 +163,11 @@ typedef struct {
                                  persistent kernel, Sigma copy-out); needs D on the device;
                                  the graph is re-captured when the D or Sigma pointers change */
   const char *tuning_db;      /* text file written by the autotuner, or NULL: one choice per line,
-                                   hfxtune1 <key> tile_r=<32|64> tier_tau=<x> tier_tau_bf=<x>
+                                   hfxtune1 <key> tile_r=<32|64|128> tier_tau=<x> tier_tau_bf=<x>
                                  where <key> is hfx_tune_key's string of the plan; the last
                                  line with the plan's key is used                            */
   int32_t tile_r;             /* column width of the output blocks of the terms-3/4 product:
-                                 32 or 64; 0: the tuning file's choice, else 64             */
+                                 32, 64 or 128; 0: the tuning file's choice, else 64        */
 } hfx_options;
 
 typedef struct {               /* filled by hfx_build when non-NULL (synchronises)          */

@@ -119,7 +119,7 @@ struct ItemLds {
   double H1[MAXN * MAXN];
   double DAB[MAXN * MAXN];
   // GEMM block bookkeeping
-  unsigned blk_act;
+  unsigned long long blk_act;  // active 16x16 tiles of the current output block (bit: wave * tiles + tile)
   unsigned blk_ub;  // largest stage-2 bound (float bits) of the kept units of the current block
   int t1any, kc, nsel;
   unsigned long long t2any;
@@ -718,7 +718,8 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 // for a load before then, and fetches and stores run also past the end of K (clamped loads,
 // zeros stored): with no branch around them the compiler knows how many loads are in flight at
 // each store and waits only for the older chunk's.
-constexpr int BM = 128, BN = 64, BK = 16;  // BN: the widest block (stage sizes, terms 1 and 2)
+constexpr int BM = 128, BN = 64, BK = 16;  // BN: the column width of the terms-1/2 blocks
+constexpr int BNR = 128;                    // the widest terms-3/4 block (B stage size)
 
 // x where ok, else +0 (bitwise: no branch, and no NaN or Inf of x survives)
 __device__ __forceinline__ double keep_if(double x, bool ok) {
@@ -762,8 +763,7 @@ __device__ __forceinline__ void chunk_pipeline(int K, bool active, Fetch fetch, 
 }
 
 // FP64 (v_mfma_f64_16x16x4f64), BK = 16 K per chunk: four A elements (row tid&127) and W/32 B
-// elements (column tid%W) per thread; per K step a wave reads its A fragment and all W/16 B
-// fragments from LDS before the step's MFMAs.
+// elements (column tid%W) per thread.
 template <int W, class AAt, class BAt>
 __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, bool aok, int Ka, bool bok, unsigned act,
                                             double *As, double *Bs, d4 (&acc)[W / 16]) {
@@ -776,31 +776,39 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, bool aok,
   struct Regs {
     double a[4], b[NBF];
   };
-  chunk_pipeline<BK, Regs>(
-      K, true,
-      [&](int k0, Regs &r) {
+  auto fetch = [&](int k0, Regs &r) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) r.a[s] = a_at(min(k0 + akq + s, K - 1));
+    for (int s = 0; s < 4; ++s) r.a[s] = a_at(min(k0 + akq + s, K - 1));
 #pragma unroll
-        for (int q = 0; q < NBF; ++q) r.b[q] = b_at(min(k0 + bk + q * RS, K - 1));
-      },
-      [&](int st, int k0, const Regs &r) {
-        double *a = As + st * BK * BM, *b = Bs + st * BK * W;
+    for (int q = 0; q < NBF; ++q) r.b[q] = b_at(min(k0 + bk + q * RS, K - 1));
+  };
+  auto stash = [&](int st, int k0, const Regs &r) {
+    double *a = As + st * BK * BM, *b = Bs + st * BK * W;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = keep_if(r.a[s], aok & (k0 + akq + s < Ka));
+    for (int s = 0; s < 4; ++s) a[(akq + s) * BM + ar] = keep_if(r.a[s], aok & (k0 + akq + s < Ka));
 #pragma unroll
-        for (int q = 0; q < NBF; ++q) b[(bk + q * RS) * W + bc] = keep_if(r.b[q], bok & (k0 + bk + q * RS < K));
-      },
-      [&](int st) {  // every tile of an active wave: a branch per tile would split the block
-        const double *a = As + st * BK * BM + wave * 16 + l16, *b = Bs + st * BK * W + l16;
+    for (int q = 0; q < NBF; ++q) b[(bk + q * RS) * W + bc] = keep_if(r.b[q], bok & (k0 + bk + q * RS < K));
+  };
+  // MFMAs of stage st for the tiles in m (all of them: branch-free, so that the step stays one
+  // basic block; some: a wave-uniform branch per tile)
+  auto compute = [&](int st, unsigned m, bool all) {
+    const double *a = As + st * BK * BM + wave * 16 + l16, *b = Bs + st * BK * W + l16;
 #pragma unroll
-        for (int s = 0; s < BK / 4; ++s) {
-          const int kr = 4 * s + kk;
-          const double av = a[kr * BM];
+    for (int s = 0; s < BK / 4; ++s) {
+      const int kr = 4 * s + kk;
+      const double av = a[kr * BM];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) acc[v] = mfma64(av, b[kr * W + v * 16], acc[v]);
-        }
-      });
+      for (int v = 0; v < NV; ++v)
+        if (all || (m & (1u << v))) acc[v] = mfma64(av, b[kr * W + v * 16], acc[v]);
+    }
+  };
+  // a wave with every tile active runs the branch-free step; one with some, the per-tile one
+  // (at W = 128 the second copy of the pipeline spills registers: every tile of an active wave)
+  constexpr unsigned FULL = (1u << NV) - 1u;
+  if (W > 64 || actw == FULL)
+    chunk_pipeline<BK, Regs>(K, actw != 0, fetch, stash, [&](int st) { compute(st, FULL, true); });
+  else
+    chunk_pipeline<BK, Regs>(K, actw != 0, fetch, stash, [&](int st) { compute(st, actw, false); });
 }
 
 // FP32 (v_mfma_f32_16x16x4f32), BKF K per chunk: BKF/4 A elements (row tid&127, k rows
@@ -822,32 +830,32 @@ __device__ __forceinline__ void wg_block_mm32(int K, AAt a_at, BAt b_at, bool ao
     float a[NA];
     double b[NB];
   };
-  chunk_pipeline<BKF, Regs>(
-      K, actw != 0,
-      [&](int k0, Regs &r) {
+  auto fetch = [&](int k0, Regs &r) {
 #pragma unroll
-        for (int s = 0; s < NA; ++s) r.a[s] = a_at(min(k0 + akq + s, K - 1));
+    for (int s = 0; s < NA; ++s) r.a[s] = a_at(min(k0 + akq + s, K - 1));
 #pragma unroll
-        for (int q = 0; q < NB; ++q) r.b[q] = b_at(min(k0 + bk + RS * q, K - 1));
-      },
-      [&](int st, int k0, const Regs &r) {
-        float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
+    for (int q = 0; q < NB; ++q) r.b[q] = b_at(min(k0 + bk + RS * q, K - 1));
+  };
+  auto stash = [&](int st, int k0, const Regs &r) {
+    float *a = As + st * BKF * BM, *b = Bs + st * BKF * W;
 #pragma unroll
-        for (int s = 0; s < NA; ++s) a[(akq + s) * BM + ar] = keep_if(r.a[s], aok & (k0 + akq + s < Ka));
+    for (int s = 0; s < NA; ++s) a[(akq + s) * BM + ar] = keep_if(r.a[s], aok & (k0 + akq + s < Ka));
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
-          b[(bk + RS * q) * W + bc] = keep_if((float)r.b[q], bok & (k0 + bk + RS * q < K));
-      },
-      [&](int st) {  // every tile of an active wave
-        const float *a = As + st * BKF * BM + wave * 16 + l16, *b = Bs + st * BKF * W + l16;
+    for (int q = 0; q < NB; ++q)
+      b[(bk + RS * q) * W + bc] = keep_if((float)r.b[q], bok & (k0 + bk + RS * q < K));
+  };
+  // every tile of an active wave, branch-free (a second, per-tile copy of the pipeline as in the
+  // FP64 form spills registers in the kernels that hold both forms)
+  chunk_pipeline<BKF, Regs>(K, actw != 0, fetch, stash, [&](int st) {
+    const float *a = As + st * BKF * BM + wave * 16 + l16, *b = Bs + st * BKF * W + l16;
 #pragma unroll
-        for (int s = 0; s < BKF / 4; ++s) {
-          const int kr = 4 * s + kk;
-          const float av = a[kr * BM];
+    for (int s = 0; s < BKF / 4; ++s) {
+      const int kr = 4 * s + kk;
+      const float av = a[kr * BM];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) acc[v] = mfma32(av, b[kr * W + v * 16], acc[v]);
-        }
-      });
+      for (int v = 0; v < NV; ++v) acc[v] = mfma32(av, b[kr * W + v * 16], acc[v]);
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -873,7 +881,7 @@ __device__ __forceinline__ void wg_block_mm_bf3(int K, AAt a_at, BAt b_at, bool 
                                                 uint16_t *As, uint16_t *Bs, f4 (&acc)[W / 16]) {
   constexpr int NV = W / 16, KB = BKB * W / NT;  // B elements per thread and chunk (4 or 2)
   constexpr int ASZ = 2 * BM * BKB, BSZ = 2 * W * BKB;  // one stage: hi block then lo block
-  static_assert(2 * ASZ * 2 <= 2 * BK * BM * 8 && 2 * BSZ * 2 <= 2 * BK * BN * 8, "BF16 stages fit the FP64 ones");
+  static_assert(2 * ASZ * 2 <= 2 * BK * BM * 8 && 2 * BSZ * 2 <= 2 * BK * BNR * 8, "BF16 stages fit the FP64 ones");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kg = lane >> 4, l16 = lane & 15;
   const int ar = tid & (BM - 1), ako = (tid >> 7) * 8;
   const int bc = tid & (W - 1), bko = (tid / W) * KB;
@@ -952,8 +960,8 @@ __device__ __forceinline__ bool tile_has(const ItemLds &L, const gmem<const uint
 // GEMM-R: terms 3 and 4.  Rows (F,f), K = (alpha,a), columns (G, [g | b]):
 //   out[(F,f)][(G,g)] = sum_{al,a} C_AF[al][a][f] T4_G[al][a][g]  -> Sigma(F,G)  (term 4)
 //   out[(F,f)][(G,b)] = sum_{al,a} C_AF[al][a][f] T3_G[al][a][b]  -> summed over G into Sigma(F,B)
-// 128 x W blocks (W = 64 or 32, the plan's tile_r) in row-block-major order; a block whose tiles
-// hold no kept unit is skipped.
+// 128 x W blocks (W = 128, 64 or 32, the plan's tile_r) in row-block-major order; a block whose
+// tiles hold no kept unit is skipped.
 // PR: the precision forms compiled in (0: FP64 only; 1: FP64 and FP32; 2: FP64, FP32 and
 // split-BF16x3), so that a plan's kernel carries no code, and no registers, for forms it never runs.
 template <int W, int PR>
@@ -985,24 +993,24 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
         L.blk_ub = 0u;
       }
       __syncthreads();
-      if (tid < 8 * NCT * 16) {
-        const int sidx = tid >> 4, wr = sidx / NCT, ct = sidx % NCT;
-        const int rr = rb * BM + wr * 16 + (tid & 15);
+      for (int t = tid; t < 8 * NCT * 16; t += NT) {
+        const int sidx = t >> 4, wr = sidx / NCT, ct = sidx % NCT;
+        const int rr = rb * BM + wr * 16 + (t & 15);
         if (rr < L.MR) {
           const int c_lo = cb * W + ct * 16, c_hi = min(c_lo + 16, L.NR);
           if (tile_has(L, mask, col2jj, row2i[rr], c_lo, c_hi, kT4, kT3)) {
-            atomicOr(&L.blk_act, 1u << sidx);
+            atomicOr(&L.blk_act, 1ull << sidx);
             if (tiered) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, row2i[rr], c_lo, c_hi, 1)));
           }
         }
       }
       __syncthreads();
-      const unsigned act_all = L.blk_act;
+      const unsigned long long act_all = L.blk_act;
       if (!act_all) continue;
       const float bub = __uint_as_float(L.blk_ub);
       const bool bf = PR == 2 && tier == 3 && bub <= tau_bf;
       const bool fp32 = PR >= 1 && (bf || tier == 2 || (tiered && bub <= tau));
-      const unsigned act = (act_all >> (NCT * wave)) & ((1u << NCT) - 1u);
+      const unsigned act = (unsigned)((act_all >> (NCT * wave)) & ((1ull << NCT) - 1ull));
       const int c = cb * W + (tid & (W - 1));
       const bool cok = c < L.NR;
       const gmem<const double> *Bb = slot;
@@ -1055,11 +1063,11 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
         wg_block_mm<W>(
             K, [&](int k) { return Ab[(long long)k * As_]; }, [&](int k) { return Bb[(long long)k * Bstr]; }, rok, K,
             cok, act, As, Bs, acc);
-        nmfma += (unsigned long long)(act ? NCT : 0) * ((K + 3) >> 2);
+        nmfma += (unsigned long long)(W > 64 ? (act ? NCT : 0) : __builtin_popcount(act)) * ((K + 3) >> 2);
       }
-      // epilogue of this wave's tiles: the (F,G) records of all its elements are loaded before
-      // the first atomic, so that the loads overlap one another
-      int ei[4], ef[4], vj[NCT], vc[NCT], vn[NCT];
+      // epilogue of this wave's tiles, four at a time: the (F,G) records of their elements are
+      // loaded before the first atomic, so that the loads overlap one another
+      int ei[4], ef[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int rr = rb * BM + wave * 16 + (fp32 ? 4 * kk + e : kk + 4 * e);  // result row (MFMA form)
@@ -1067,40 +1075,46 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
         ef[e] = ei[e] >= 0 ? rr - L.f_row0[ei[e]] : 0;
       }
 #pragma unroll
-      for (int v = 0; v < NCT; ++v) {
-        const int cc0 = cb * W + v * 16 + l16;
-        const bool ok = (act & (1u << v)) && cc0 < L.NR;
-        const int jj = ok ? col2jj[cc0] : 0, j = L.a_j[jj];
-        vj[v] = ok ? j : -1;
-        vc[v] = cc0 - L.a_col0[jj];
-        vn[v] = L.g_n[j];
-      }
-      uint8_t ubits[NCT][4];
-      long long uoff[NCT][4];
+      for (int h = 0; h < NCT; h += 4) {
+        constexpr int NH = NCT < 4 ? NCT : 4;
+        int vj[NH], vc[NH], vn[NH];
 #pragma unroll
-      for (int v = 0; v < NCT; ++v)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool ok = vj[v] >= 0 && ei[e] >= 0;
-          const int q = ok ? ei[e] * L.nG + vj[v] : 0;
-          ubits[v][e] = ok ? mask[q] : 0;
-          uoff[v][e] = doff[q];
+        for (int u = 0; u < NH; ++u) {
+          const int cc0 = cb * W + (h + u) * 16 + l16;
+          const bool ok = (act & (1u << (h + u))) && cc0 < L.NR;
+          const int jj = ok ? col2jj[cc0] : 0, j = L.a_j[jj];
+          vj[u] = ok ? j : -1;
+          vc[u] = cc0 - L.a_col0[jj];
+          vn[u] = L.g_n[j];
         }
+        uint8_t ubits[NH][4];
+        long long uoff[NH][4];
 #pragma unroll
-      for (int v = 0; v < NCT; ++v)
+        for (int u = 0; u < NH; ++u)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint8_t bits = ubits[v][e];
-          if (!(bits & (kT3 | kT4))) continue;
-          const int i = ei[e], j = vj[v], cc = vc[v], ng = vn[v];
-          const double w = unit_weight(L, i, j);
-          if (cc < ng) {
-            if (bits & kT4) gatomic_add(Sbuf + uoff[v][e] + ef[e] * ng + cc, -w * acc[v][e]);
-          } else if (bits & kT3) {
-            atomicAdd(&acc3[(fp32 ? 4 * kk + e : kk + 4 * e) * ld3 + (cc - ng)], -w * acc[v][e]);
-            any3 = true;
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = vj[u] >= 0 && ei[e] >= 0;
+            const int q = ok ? ei[e] * L.nG + vj[u] : 0;
+            ubits[u][e] = ok ? mask[q] : 0;
+            uoff[u][e] = doff[q];
           }
-        }
+#pragma unroll
+        for (int u = 0; u < NH; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const uint8_t bits = ubits[u][e];
+            if (!(bits & (kT3 | kT4))) continue;
+            const int i = ei[e], j = vj[u], cc = vc[u], ng = vn[u];
+            const double w = unit_weight(L, i, j);
+            const double x = acc[h + u][e];
+            if (cc < ng) {
+              if (bits & kT4) gatomic_add(Sbuf + uoff[u][e] + ef[e] * ng + cc, -w * x);
+            } else if (bits & kT3) {
+              atomicAdd(&acc3[(fp32 ? 4 * kk + e : kk + 4 * e) * ld3 + (cc - ng)], -w * x);
+              any3 = true;
+            }
+          }
+      }
     }
     // flush term 3 of this wave's 16 rows: Sigma(F,B)[f][b]
     if (__any(any3)) {
@@ -1263,7 +1277,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
       if (hit) {
         for (int ct = 0; ct < 4; ++ct) {
           const int cl = c0 + ct * 16;
-          if (tile_has(L, mask, col2jj, i, cl, min(cl + 16, c1), kT1, kT2)) atomicOr(&L.blk_act, 1u << ct);
+          if (tile_has(L, mask, col2jj, i, cl, min(cl + 16, c1), kT1, kT2)) atomicOr(&L.blk_act, 1ull << ct);
         }
         if (tier == 1 || tier == 3) atomicMax(&L.blk_ub, __float_as_uint(cols_ub(L, ub, col2jj, i, c0, c1, 0)));
       }
@@ -1327,7 +1341,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
     }
     __threadfence_block();
     __syncthreads();
-    const unsigned colact = L.blk_act & 15u;
+    const unsigned colact = (unsigned)(L.blk_act & 15ull);
     for (int rb = 0; rb < nrb; ++rb) {
       const int r = rb * BM + (tid & (BM - 1));
       const bool rok = r < M;
@@ -1354,7 +1368,7 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
         wg_block_mm<BN>(
             Kc, [&](int k) { return CT[max(kaddr[k], 0ll) + rc]; }, [&](int k) { return panel[(long long)k * BN + bcl]; },
             rok, kc, true, act, As, Bs, acc);
-        nmfma += (unsigned long long)(act ? 4 : 0) * (Kc >> 2);
+        nmfma += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
@@ -1388,9 +1402,9 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
   short *col2jj = reinterpret_cast<short *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap);
   double *As = reinterpret_cast<double *>(reinterpret_cast<uint8_t *>(dyn) + kp.rows_cap + 2 * kp.cols_cap);
   double *Bs = As + 2 * BK * BM;
-  double *acc3 = Bs + 2 * BK * BN;  // [NW][16][ld3]
+  double *acc3 = Bs + 2 * BK * BNR;  // [NW][16][ld3]
   long long *kaddr = reinterpret_cast<long long *>(acc3 + NW * 16 * kp.ld3);  // [rows_cap]
-  const int dyn_doubles = 2 * BK * BM + 2 * BK * BN + NW * 16 * kp.ld3;
+  const int dyn_doubles = 2 * BK * BM + 2 * BK * BNR + NW * 16 * kp.ld3;
   __shared__ int s_item;
   const int tid = threadIdx.x;
   gmem<double> *slot = gptr(P.scratch) + (long long)blockIdx.x * P.slot_doubles;
@@ -1925,7 +1939,7 @@ __global__ __launch_bounds__(256) void k_energy(const double *__restrict__ D, co
 // ---------------------------------------------------------------------------------------------
 // launch wrappers (host side)
 size_t main_dyn_lds(int rows_cap, int cols_cap, int ld3) {
-  return (size_t)rows_cap + 2 * (size_t)cols_cap + (size_t)(2 * BK * BM + 2 * BK * BN + NW * 16 * ld3) * sizeof(double) +
+  return (size_t)rows_cap + 2 * (size_t)cols_cap + (size_t)(2 * BK * BM + 2 * BK * BNR + NW * 16 * ld3) * sizeof(double) +
          (size_t)rows_cap * sizeof(long long);
 }
 
@@ -1936,8 +1950,9 @@ hipError_t launch_to_f32(const double *src, float *dst, long long n, hipStream_t
 
 hipError_t main_set_lds(int rows_cap, int cols_cap, int ld3) {
   const size_t dyn = main_dyn_lds(rows_cap, cols_cap, ld3);
-  const void *fns[] = {(const void *)k_main<64, 0>, (const void *)k_main<32, 0>, (const void *)k_main<64, 1>,
-                       (const void *)k_main<32, 1>, (const void *)k_main<64, 2>, (const void *)k_main<32, 2>};
+  const void *fns[] = {(const void *)k_main<64, 0>,  (const void *)k_main<32, 0>, (const void *)k_main<128, 0>,
+                       (const void *)k_main<64, 1>,  (const void *)k_main<32, 1>, (const void *)k_main<128, 1>,
+                       (const void *)k_main<64, 2>,  (const void *)k_main<32, 2>, (const void *)k_main<128, 2>};
   for (const void *f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
@@ -1960,6 +1975,10 @@ hipError_t launch_main(const DevPlan &P, int n_slots, int rows_cap, int cols_cap
     if (pr == 0) hipLaunchKernelGGL((k_main<32, 0>), g, b, dyn, s, P, kp);
     if (pr == 1) hipLaunchKernelGGL((k_main<32, 1>), g, b, dyn, s, P, kp);
     if (pr == 2) hipLaunchKernelGGL((k_main<32, 2>), g, b, dyn, s, P, kp);
+  } else if (tile_r == 128) {
+    if (pr == 0) hipLaunchKernelGGL((k_main<128, 0>), g, b, dyn, s, P, kp);
+    if (pr == 1) hipLaunchKernelGGL((k_main<128, 1>), g, b, dyn, s, P, kp);
+    if (pr == 2) hipLaunchKernelGGL((k_main<128, 2>), g, b, dyn, s, P, kp);
   } else {
     if (pr == 0) hipLaunchKernelGGL((k_main<64, 0>), g, b, dyn, s, P, kp);
     if (pr == 1) hipLaunchKernelGGL((k_main<64, 1>), g, b, dyn, s, P, kp);

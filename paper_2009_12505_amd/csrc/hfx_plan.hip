@@ -419,7 +419,8 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
     return fail(HFX_ERR_ARG, "unknown precision %d", o.precision);
   if (!std::isfinite(o.tier_tau) || !std::isfinite(o.tier_tau_bf))
     return fail(HFX_ERR_ARG, "tier_tau must be finite and >= 0 (or < 0 to take it from the tuning file)");
-  if (o.tile_r != 0 && o.tile_r != 32 && o.tile_r != 64) return fail(HFX_ERR_ARG, "tile_r must be 0, 32 or 64");
+  if (o.tile_r != 0 && o.tile_r != 32 && o.tile_r != 64 && o.tile_r != 128)
+    return fail(HFX_ERR_ARG, "tile_r must be 0, 32, 64 or 128");
   if (o.scheduler < HFX_SCHED_PLAN || o.scheduler > HFX_SCHED_KMEANS)
     return fail(HFX_ERR_ARG, "unknown scheduler %d", o.scheduler);
   if (o.scheduler == HFX_SCHED_MLP && !o.mlp_weights)
@@ -500,8 +501,8 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
         }
       }
       std::fclose(fp);
-      if (t_tile != 0 && t_tile != 32 && t_tile != 64)
-        return fail(HFX_ERR_ARG, "tuning_db '%s': tile_r %d for '%s' is not 32 or 64", o.tuning_db, t_tile,
+      if (t_tile != 0 && t_tile != 32 && t_tile != 64 && t_tile != 128)
+        return fail(HFX_ERR_ARG, "tuning_db '%s': tile_r %d for '%s' is not 32, 64 or 128", o.tuning_db, t_tile,
                     p->tune_key.c_str());
     }
     p->tile_r = o.tile_r ? o.tile_r : (t_tile ? t_tile : 64);

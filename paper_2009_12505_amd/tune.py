@@ -2,7 +2,7 @@
 
 For one plan key (the species present, the CS-matrix threshold and the precision form, as
 hfx_tune_key reports it) it times the candidate column widths of the terms-3/4 output blocks
-(tile_r 64 or 32) and, for the tiered forms, candidate tier bounds (tier_tau; tier_tau_bf for the
+(tile_r 128, 64 or 32) and, for the tiered forms, candidate tier bounds (tier_tau; tier_tau_bf for the
 split-BF16x3 tier) on a calibration subset of home atoms.  A candidate is admitted only if its
 Sigma and E_x on that subset differ from the FP64 build of the same subset by at most a third of
 the method's targets (1e-7 max-abs in Sigma, 1e-8 Ha per home atom in E_x); the fastest admitted
@@ -49,7 +49,7 @@ def _builds(plan, D, reps):
     return sig, float(np.median(ms))
 
 
-def tune(cells, C, V, D_pattern, D, thresholds, precision, home_subset, db_path=None, tiles=(64, 32),
+def tune(cells, C, V, D_pattern, D, thresholds, precision, home_subset, db_path=None, tiles=(128, 64, 32),
          taus=(1e-4, 1e-3, 1e-2), taus_bf=(1e-6, 1e-5, 1e-4), reps: int = 2, log=print):
     """Tune one plan key on the given home subset; returns (key, best Candidate, all candidates).
     The best choice is appended to ``db_path`` when given."""

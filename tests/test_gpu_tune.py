@@ -1,7 +1,7 @@
 """Tile shapes, the split-BF16x3 tier and the autotuner against the FP64 oracle.
 
-* tile_r = 32 (narrower terms-3/4 output blocks) gives the same Sigma as the oracle to FP64
-  summation order, like the default 64.
+* tile_r = 32 and 128 (narrower and wider terms-3/4 output blocks) give the same Sigma as the
+  oracle to FP64 summation order, like the default 64.
 * HFX_PREC_BF16X3: three tiers (FP64 / FP32 / split-BF16x3 by the stage-2 bounds of a block's
   kept units) meet the method's target (1e-7 max-abs Sigma, 1e-8 Ha per atom) with small tier
   bounds; with every terms-3/4 block forced into split-BF16x3 the error stays within a bound of
@@ -25,20 +25,21 @@ def _ref(w):
     return ref, oracle.energy(cell, w.D[0], ref.sigma)
 
 
+@pytest.mark.parametrize("tile", [32, 128])
 @pytest.mark.parametrize("cfg", [1, 4, 5, 6])
-def test_tile_r_32_matches_oracle(cfg):
-    log(f"case tile_r 32 tiny[{cfg}]")
+def test_tile_r_matches_oracle(cfg, tile):
+    log(f"case tile_r {tile} tiny[{cfg}]")
     w = hs.make_workload("tiny", **TINY[cfg])
     ref, e_ref = _ref(w)
-    sig, e, st = gpu_build(w, tile_r=32)
-    assert st["tile_r"] == 32
-    check_close(sig[0], ref.sigma, label=f"tile_r 32 tiny[{cfg}]")
+    sig, e, st = gpu_build(w, tile_r=tile)
+    assert st["tile_r"] == tile
+    check_close(sig[0], ref.sigma, label=f"tile_r {tile} tiny[{cfg}]")
     assert abs(e[0] - e_ref) <= 1e-11 * abs(e_ref)
     for t in (1, 2, 3, 4):
         assert st[f"kept_s3_t{t}"] == ref.stats[f"kept_s3_t{t}"]
 
 
-@pytest.mark.parametrize("cfg,tile", [(1, 64), (4, 64), (5, 32), (6, 64)])
+@pytest.mark.parametrize("cfg,tile", [(1, 64), (4, 128), (5, 32), (6, 64)])
 def test_bf16x3_tiers_meet_the_target(cfg, tile):
     from paper_2009_12505_amd import PREC_BF16X3
     log(f"case bf16x3 tiny[{cfg}] tile_r {tile}")
@@ -75,7 +76,7 @@ def test_tuner_files_a_choice_the_plan_uses(tmp_path):
     home = list(range(w.cells[0].n_atoms))
     db = tmp_path / "tune.txt"
     key, best, cands = tune.tune(w.cells, w.C, w.V, w.D, w.D, w.thresholds, PREC_TIERED, home, db_path=db,
-                                 tiles=(64, 32), taus=(1e-4, 1e-3), reps=1, log=log)
+                                 tiles=(128, 64), taus=(1e-4, 1e-3), reps=1, log=log)
     assert len(cands) == 4 and best.admitted
     line = db.read_text().strip().splitlines()[-1]
     assert line.startswith(f"hfxtune1 {key} tile_r={best.tile_r} ")
