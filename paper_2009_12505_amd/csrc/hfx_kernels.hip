@@ -42,6 +42,12 @@ __device__ __forceinline__ gmem<T> *gptr(T *p) {
 }
 template <class T>
 using smem = __attribute__((address_space(3))) T;  // LDS
+
+// x where ok, else +0 (bitwise: no branch, and no NaN or Inf of x survives)
+__device__ __forceinline__ double keep_if(double x, bool ok) {
+  return __longlong_as_double(__double_as_longlong(x) & -(long long)ok);
+}
+__device__ __forceinline__ float keep_if(float x, bool ok) { return __int_as_float(__float_as_int(x) & -(int)ok); }
 __device__ __forceinline__ void gatomic_add(gmem<double> *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -248,6 +254,23 @@ __device__ __forceinline__ d4 tile_mm_burst(int K, FA fa, FB fb, d4 acc) {
   return acc;
 }
 
+// step(t, buffer) for t in [0, n), the loads of step t+1 (load(t+1, buffer)) issued before the
+// MFMAs of step t, in two register buffers; load takes in-bounds addresses for every t < n
+template <class Buf, class Load, class Step>
+__device__ __forceinline__ void pipelined(int n, Load load, Step step) {
+  if (n <= 0) return;
+  Buf b0, b1;
+  load(0, b0);
+  int t = 0;
+  for (; t + 1 < n; t += 2) {
+    load(t + 1, b1);
+    step(t, b0);
+    load(min(t + 2, n - 1), b0);
+    step(t + 1, b1);
+  }
+  if (t < n) step(t, b0);
+}
+
 // ---------------------------------------------------------------------------------------------
 // G side for one alive G, by one wave: Y = V_AB C_BG, T4 = D_AB Y, T3 = Y D_AG^T (per alpha),
 // the Gram matrices N1[b] = Y_b^T Y_b and M2[g] = Y_g^T Y_g, and the slice norms of stages 2, 3.
@@ -269,45 +292,52 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<doubl
       return Vg[q];
   };
   unsigned long long nm = 0;
-  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]; four alpha tiles share each C fragment,
-  // which is fetched 32 K at a time before its MFMAs
-  const int mt = (PA + 15) >> 4, nt = (N + 15) >> 4;
+  // Y[al][b*ng+g] = sum_be V[al][be] C[be][b*ng+g]; four alpha tiles share each C fragment, which
+  // is fetched 32 K at a time, the next fragment's loads in flight during the current's MFMAs
+  const int mt = (PA + 15) >> 4, nt = (N + 15) >> 4, nkc = (PB + 31) >> 5;
+  struct YB {
+    double v[8];
+  };
   for (int rg = 0; rg < mt; rg += 4) {
-    for (int ct = 0; ct < nt; ++ct) {
-      const int col = (ct << 4) + l16;
-      const bool cok = col < N;
-      d4 acc[4];
+    d4 acc[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
-      for (int k0 = 0; k0 < PB; k0 += 32) {
-        double bv[8];
+    for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
+    pipelined<YB>(
+        nt * nkc,
+        [&](int t, YB &bb) {
+          const int ct = t / nkc, k0 = (t - ct * nkc) << 5, col = min((ct << 4) + l16, N - 1);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int k = k0 + 4 * s + kk;
-          bv[s] = (cok && k < PB) ? C[(long long)k * N + col] : 0.0;
-        }
+          for (int s = 0; s < 8; ++s) bb.v[s] = C[(long long)min(k0 + 4 * s + kk, PB - 1) * N + col];
+        },
+        [&](int t, const YB &bb) {
+          const int ct = t / nkc, k0 = (t - ct * nkc) << 5, col = (ct << 4) + l16;
+          const bool cok = col < N;
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          if (k0 + 4 * s >= PB) break;
-          const int k = k0 + 4 * s + kk;
+          for (int s = 0; s < 8; ++s) {
+            if (k0 + 4 * s >= PB) break;
+            const int k = k0 + 4 * s + kk;
+            const double b = keep_if(bb.v[s], cok & (k < PB));
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if (rg + u >= mt) break;
-            const int row = ((rg + u) << 4) + l16;
-            const double a = (row < PA && k < PB) ? vat(row * PB + k) : 0.0;
-            acc[u] = mfma64(a, bv[s], acc[u]);
+            for (int u = 0; u < 4; ++u) {
+              if (rg + u >= mt) break;
+              const int row = ((rg + u) << 4) + l16;
+              const double a = (row < PA && k < PB) ? vat(row * PB + k) : 0.0;
+              acc[u] = mfma64(a, b, acc[u]);
+            }
           }
-        }
-      }
-      nm += (unsigned long long)min(4, mt - rg) * ((PB + 3) >> 2);
+          if (k0 + 32 >= PB) {  // the column tile is complete
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int r = ((rg + u) << 4) + kk + 4 * e;
-          if (rg + u < mt && r < PA && cok) Y[(long long)r * N + col] = acc[u][e];
-        }
-    }
+              for (int e = 0; e < 4; ++e) {
+                const int r = ((rg + u) << 4) + kk + 4 * e;
+                if (rg + u < mt && r < PA && cok) Y[(long long)r * N + col] = acc[u][e];
+              }
+              acc[u] = d4{0, 0, 0, 0};
+            }
+          }
+        });
+    nm += (unsigned long long)nt * min(4, mt - rg) * ((PB + 3) >> 2);
   }
   __threadfence_block();
   // T4[(al,a)][g] = sum_b D_AB[a][b] Y[al][b][g]: D_AB fragments once, two alphas' Y at a time
@@ -324,6 +354,40 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<doubl
           const int k = 4 * s + kk;
           av[s] = (a0 + l16 < na && k < nb) ? L.DAB[(a0 + l16) * nb + k] : 0.0;
         }
+        if (nb <= 16) {
+          // four alphas per step (K = nb <= 16: four K steps), the next four's loads in flight
+          struct TB {
+            double v[4][4];
+          };
+          const int gc = min(g, ng - 1);
+          pipelined<TB>(
+              (PA + 3) >> 2,
+              [&](int t, TB &bb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                  for (int s = 0; s < 4; ++s)
+                    bb.v[q][s] = Y[(long long)min(4 * t + q, PA - 1) * N + min(4 * s + kk, nb - 1) * ng + gc];
+              },
+              [&](int t, const TB &bb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int al = 4 * t + q;
+                  if (al >= PA) break;
+                  d4 h = {0, 0, 0, 0};
+#pragma unroll
+                  for (int s = 0; s < 4; ++s)
+                    if (4 * s < nb) h = mfma64(av[s], keep_if(bb.v[q][s], (4 * s + kk < nb) & (g < ng)), h);
+                  for (int e = 0; e < 4; ++e) {
+                    const int a = a0 + kk + 4 * e;
+                    if (a < na && g < ng) {
+                      T4[((long long)al * na + a) * ng + g] = h[e];
+                      sq += h[e] * h[e];
+                    }
+                  }
+                }
+              });
+        } else
         for (int al0 = 0; al0 < PA; al0 += 2) {
           double bv[2][MAXN / 4];
 #pragma unroll
@@ -373,6 +437,40 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<doubl
           const int k = 4 * s + kk;
           av[s] = (a0 + l16 < na && k < ng) ? DAG[(a0 + l16) * ng + k] : 0.0;
         }
+        if (ng <= 16) {
+          // four alphas per step (K = ng <= 16), as for T4
+          struct TB {
+            double v[4][4];
+          };
+          const int bc = min(b, nb - 1);
+          pipelined<TB>(
+              (PA + 3) >> 2,
+              [&](int t, TB &bb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                  for (int s = 0; s < 4; ++s)
+                    bb.v[q][s] = Y[(long long)min(4 * t + q, PA - 1) * N + bc * ng + min(4 * s + kk, ng - 1)];
+              },
+              [&](int t, const TB &bb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int al = 4 * t + q;
+                  if (al >= PA) break;
+                  d4 h = {0, 0, 0, 0};
+#pragma unroll
+                  for (int s = 0; s < 4; ++s)
+                    if (4 * s < ng) h = mfma64(av[s], keep_if(bb.v[q][s], (4 * s + kk < ng) & (b < nb)), h);
+                  for (int e = 0; e < 4; ++e) {
+                    const int a = a0 + kk + 4 * e;
+                    if (a < na && b < nb) {
+                      T3[((long long)al * na + a) * nb + b] = h[e];
+                      sq += h[e] * h[e];
+                    }
+                  }
+                }
+              });
+        } else
         for (int al0 = 0; al0 < PA; al0 += 2) {
           double bv[2][MAXN / 4];
 #pragma unroll
@@ -409,6 +507,38 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<doubl
   // N1[b][g][g'] = sum_al Y[al][b][g] Y[al][b][g'];  Yb^2 = max_b trace N1[b]
   gmem<double> *N1 = slot + L.a_n1[jj];
   double ybmax = 0.0;
+  struct GB {
+    double v[16];
+  };
+  if (ng <= 16 && PA <= 64) {
+    // one 16x16 tile per b over K = PA <= 64; both operands are the same fragment Y[k][b][l16], one
+    // load per K step; the next b's loads in flight during the current's MFMAs
+    const int gl = min(l16, ng - 1);
+    pipelined<GB>(
+        nb,
+        [&](int b, GB &bb) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) bb.v[s] = Y[(long long)min(4 * s + kk, PA - 1) * N + b * ng + gl];
+        },
+        [&](int b, const GB &bb) {
+          d4 h = {0, 0, 0, 0};
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            if (4 * s >= PA) break;
+            const double y = keep_if(bb.v[s], (4 * s + kk < PA) & (l16 < ng));
+            h = mfma64(y, y, h);
+          }
+          double tr = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const int g = kk + 4 * e, g2 = l16;
+            if (g < ng && g2 < ng) {
+              N1[((long long)b * ng + g) * ng + g2] = h[e];
+              if (g == g2) tr += h[e];
+            }
+          }
+          ybmax = fmax(ybmax, wave_sum(tr));
+        });
+  } else
   for (int b = 0; b < nb; ++b) {
     double tr = 0.0;
     for (int g0 = 0; g0 < ng; g0 += 16)
@@ -434,6 +564,34 @@ __device__ __noinline__ void gside_wave(const DevPlan &P, ItemLds &L, gmem<doubl
   // M2[g][b][b'] = sum_al Y[al][b][g] Y[al][b'][g];  Yg^2 = max_g trace M2[g]
   gmem<double> *M2 = slot + L.a_m2[jj];
   double ygmax = 0.0;
+  if (nb <= 16 && PA <= 64) {
+    // as N1: one tile per g, both operands the fragment Y[k][l16][g]
+    const int bl = min(l16, nb - 1);
+    pipelined<GB>(
+        ng,
+        [&](int g, GB &bb) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) bb.v[s] = Y[(long long)min(4 * s + kk, PA - 1) * N + bl * ng + g];
+        },
+        [&](int g, const GB &bb) {
+          d4 h = {0, 0, 0, 0};
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            if (4 * s >= PA) break;
+            const double y = keep_if(bb.v[s], (4 * s + kk < PA) & (l16 < nb));
+            h = mfma64(y, y, h);
+          }
+          double tr = 0.0;
+          for (int e = 0; e < 4; ++e) {
+            const int b = kk + 4 * e, b2 = l16;
+            if (b < nb && b2 < nb) {
+              M2[((long long)g * nb + b) * nb + b2] = h[e];
+              if (b == b2) tr += h[e];
+            }
+          }
+          ygmax = fmax(ygmax, wave_sum(tr));
+        });
+  } else
   for (int g = 0; g < ng; ++g) {
     double tr = 0.0;
     for (int b0 = 0; b0 < nb; b0 += 16)
@@ -720,12 +878,6 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 // each store and waits only for the older chunk's.
 constexpr int BM = 128, BN = 64, BK = 16;  // BN: the column width of the terms-1/2 blocks
 constexpr int BNR = 128;                    // the widest terms-3/4 block (B stage size)
-
-// x where ok, else +0 (bitwise: no branch, and no NaN or Inf of x survives)
-__device__ __forceinline__ double keep_if(double x, bool ok) {
-  return __longlong_as_double(__double_as_longlong(x) & -(long long)ok);
-}
-__device__ __forceinline__ float keep_if(float x, bool ok) { return __int_as_float(__float_as_int(x) & -(int)ok); }
 
 // The chunk pipeline shared by the block products.  R: one chunk's registers; fetch(k0, R&)
 // loads chunk k0, stash(st, k0, const R&) stores it into stage st, compute(st) runs the MFMAs of
