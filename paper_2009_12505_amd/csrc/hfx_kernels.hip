@@ -271,6 +271,38 @@ __device__ __forceinline__ void pipelined(int n, Load load, Step step) {
   if (t < n) step(t, b0);
 }
 
+// a 16x16 FP64 tile product over a long K, eight K steps per step of the pipeline above (the next
+// eight steps' loads in flight during the current's MFMAs); fa(row, k) and fb(k, col) load from
+// in-bounds addresses for every row, col < 16 and k < K (rows and columns past the operands give
+// output rows and columns the caller ignores); K steps past K count as zero
+template <class FA, class FB>
+__device__ __forceinline__ d4 tile_mm_long(int K, FA fa, FB fb) {
+  const int lane = threadIdx.x & 63, kk = lane >> 4, l16 = lane & 15;
+  struct KB {
+    double a[8], b[8];
+  };
+  d4 acc = {0, 0, 0, 0};
+  pipelined<KB>(
+      (K + 31) >> 5,
+      [&](int t, KB &bb) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = min(32 * t + 4 * s + kk, K - 1);
+          bb.a[s] = fa(l16, k);
+          bb.b[s] = fb(k, l16);
+        }
+      },
+      [&](int t, const KB &bb) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          if (32 * t + 4 * s >= K) break;
+          const bool ok = 32 * t + 4 * s + kk < K;
+          acc = mfma64(keep_if(bb.a[s], ok), keep_if(bb.b[s], ok), acc);
+        }
+      });
+  return acc;
+}
+
 // ---------------------------------------------------------------------------------------------
 // G side for one alive G, by one wave: Y = V_AB C_BG, T4 = D_AB Y, T3 = Y D_AG^T (per alpha),
 // the Gram matrices N1[b] = Y_b^T Y_b and M2[g] = Y_g^T Y_g, and the slice norms of stages 2, 3.
@@ -755,9 +787,9 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, co
       const int K = nb * nb;
       double smax[4] = {0.0, 0.0, 0.0, 0.0};
       for (int g0 = 0; g0 < ng; g0 += 16) {
-        const d4 h = tile_mm(
-            K, [&](int r, int k) { return ((it << 4) + r < nF && k < K) ? E2[(long long)((it << 4) + r) * K + k] : 0.0; },
-            [&](int k, int c) { return (k < K && g0 + c < ng) ? M2[(long long)(g0 + c) * K + k] : 0.0; });
+        const d4 h = tile_mm_long(
+            K, [&](int r, int k) { return E2[(long long)min((it << 4) + r, nF - 1) * K + k]; },
+            [&](int k, int c) { return M2[(long long)min(g0 + c, ng - 1) * K + k]; });
         nm += (K + 3) >> 2;
         for (int e = 0; e < 4; ++e) smax[e] = fmax(smax[e], (g0 + l16 < ng) ? h[e] : 0.0);
       }
@@ -823,9 +855,9 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, co
         __threadfence_block();
         double smax[4] = {0.0, 0.0, 0.0, 0.0};
         for (int b0 = 0; b0 < nb; b0 += 16) {
-          const d4 h = tile_mm(
-              K, [&](int r, int k) { return (r < nbat && k < K) ? E1[r * MAXN * MAXN + k] : 0.0; },
-              [&](int k, int c) { return (k < K && b0 + c < nb) ? N1[(long long)(b0 + c) * K + k] : 0.0; });
+          const d4 h = tile_mm_long(
+              K, [&](int r, int k) { return E1[min(r, nbat - 1) * MAXN * MAXN + k]; },
+              [&](int k, int c) { return N1[(long long)min(b0 + c, nb - 1) * K + k]; });
           nm += (K + 3) >> 2;
           for (int e = 0; e < 4; ++e) smax[e] = fmax(smax[e], (b0 + l16 < nb) ? h[e] : 0.0);
         }
@@ -916,7 +948,7 @@ __device__ __forceinline__ void chunk_pipeline(int K, bool active, Fetch fetch, 
 
 // FP64 (v_mfma_f64_16x16x4f64), BK = 16 K per chunk: four A elements (row tid&127) and W/32 B
 // elements (column tid%W) per thread.
-template <int W, class AAt, class BAt>
+template <int W, bool SPLIT, class AAt, class BAt>
 __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, bool aok, int Ka, bool bok, unsigned act,
                                             double *As, double *Bs, d4 (&acc)[W / 16]) {
   // As, Bs: two stages each ([2][BK][BM], [2][BK][W])
@@ -954,10 +986,11 @@ __device__ __forceinline__ void wg_block_mm(int K, AAt a_at, BAt b_at, bool aok,
         if (all || (m & (1u << v))) acc[v] = mfma64(av, b[kr * W + v * 16], acc[v]);
     }
   };
-  // a wave with every tile active runs the branch-free step; one with some, the per-tile one
-  // (at W = 128 the second copy of the pipeline spills registers: every tile of an active wave)
+  // SPLIT: a wave with every tile active runs the branch-free step, one with some the per-tile
+  // one; else every tile of an active wave (where a second copy of the pipeline would spill
+  // registers: W = 128, and the kernels that also hold the split-BF16x3 form)
   constexpr unsigned FULL = (1u << NV) - 1u;
-  if (W > 64 || actw == FULL)
+  if (!SPLIT || actw == FULL)
     chunk_pipeline<BK, Regs>(K, actw != 0, fetch, stash, [&](int st) { compute(st, FULL, true); });
   else
     chunk_pipeline<BK, Regs>(K, actw != 0, fetch, stash, [&](int st) { compute(st, actw, false); });
@@ -1212,10 +1245,10 @@ __device__ void phase_gemm_r(const DevPlan &P, ItemLds &L, const gmem<double> *s
       } else {
 #pragma unroll
         for (int v = 0; v < NCT; ++v) acc[v] = d4{0, 0, 0, 0};
-        wg_block_mm<W>(
+        wg_block_mm<W, (W <= 64 && PR < 2)>(
             K, [&](int k) { return Ab[(long long)k * As_]; }, [&](int k) { return Bb[(long long)k * Bstr]; }, rok, K,
             cok, act, As, Bs, acc);
-        nmfma += (unsigned long long)(W > 64 ? (act ? NCT : 0) : __builtin_popcount(act)) * ((K + 3) >> 2);
+        nmfma += (unsigned long long)((W <= 64 && PR < 2) ? __builtin_popcount(act) : (act ? NCT : 0)) * ((K + 3) >> 2);
       }
       // epilogue of this wave's tiles, four at a time: the (F,G) records of their elements are
       // loaded before the first atomic, so that the loads overlap one another
@@ -1517,10 +1550,10 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
-        wg_block_mm<BN>(
+        wg_block_mm<BN, (PR < 2)>(
             Kc, [&](int k) { return CT[max(kaddr[k], 0ll) + rc]; }, [&](int k) { return panel[(long long)k * BN + bcl]; },
             rok, kc, true, act, As, Bs, acc);
-        nmfma += (unsigned long long)__builtin_popcount(act) * (Kc >> 2);
+        nmfma += (unsigned long long)(PR < 2 ? __builtin_popcount(act) : (act ? 4 : 0)) * (Kc >> 2);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v)
