@@ -1410,6 +1410,66 @@ __device__ __noinline__ unsigned long long ycontract_wave(ItemLds &L, const smem
 }
 
 // ---------------------------------------------------------------------------------------------
+// GEMM-L's last row block when it holds a single row tile (rows r0..M-1, at most 16): instead of a
+// 128-row block product in which one wave of eight works, the eight waves split K, each forms the
+// 16x64 product of its K range straight from global memory (four K steps per pipeline step), and
+// the partials are summed through LDS (red: [NW][16][64] doubles, the free stage buffers) into P.
+// FP64 in every precision form.  Kept out of line (its registers would otherwise count against the
+// block products).  Returns the MFMAs issued.
+__device__ __noinline__ unsigned long long ksplit_last_block(const gmem<const double> *CT,
+                                                             const smem<const long long> *kaddr,
+                                                             const gmem<double> *panel, gmem<double> *Pb,
+                                                             smem<double> *red, int M, int Kc, int kc, int r0,
+                                                             unsigned colact) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kk = lane >> 4, l16 = lane & 15;
+  const int nks = Kc >> 2;
+  const int s0 = wave * nks / NW, s1 = (wave + 1) * nks / NW;
+  const int row = min(r0 + l16, M - 1);  // rows past M: loaded in bounds, their results dropped
+  d4 acc[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = d4{0, 0, 0, 0};
+  struct KB {
+    double a[4], b[4][4];
+  };
+  pipelined<KB>(
+      (s1 - s0 + 3) >> 2,
+      [&](int t, KB &bb) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = 4 * min(s0 + 4 * t + u, s1 - 1) + kk;
+          bb.a[u] = CT[max(kaddr[k], 0ll) + row];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) bb.b[u][v] = panel[(long long)k * BN + v * 16 + l16];
+        }
+      },
+      [&](int t, const KB &bb) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int st = s0 + 4 * t + u;
+          if (st >= s1) break;
+          const double a = keep_if(bb.a[u], 4 * st + kk < kc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (colact & (1u << v)) acc[v] = mfma64(a, bb.b[u][v], acc[v]);
+        }
+      });
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[(wave * 16 + kk + 4 * e) * BN + v * 16 + l16] = acc[v][e];
+  __syncthreads();
+  for (int q = tid; q < 16 * BN; q += NT) {
+    const int rl = q / BN, c = q - rl * BN;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += red[(w * 16 + rl) * BN + c];
+    if (r0 + rl < M) Pb[(long long)(r0 + rl) * BN + c] = ((colact >> (c >> 4)) & 1u) ? sum : 0.0;
+  }
+  return (unsigned long long)__builtin_popcount(colact) * (s1 - s0);
+}
+static_assert(NW * 16 * BN <= 2 * BK * BM + 2 * BK * BNR, "K-split partials fit the stage buffers");
+
+// ---------------------------------------------------------------------------------------------
 // GEMM-L: terms 1 and 2.  Rows (alpha,a), K = (F,f), columns (G, [g | b]).
 //   P[(al,a)][(G,g)] = sum_{F,f} C_AF[al][a][f] w D_FG[f][g]   (term 1, kept units only)
 //   P[(al,a)][(G,b)] = sum_{F,f} C_AF[al][a][f] w D_FB[f][b]   (term 2, kept units only)
@@ -1528,6 +1588,12 @@ __device__ void phase_gemm_l(const DevPlan &P, ItemLds &L, const gmem<double> *s
     __syncthreads();
     const unsigned colact = (unsigned)(L.blk_act & 15ull);
     for (int rb = 0; rb < nrb; ++rb) {
+      if (M - rb * BM <= 16) {
+        // a last row block of one row tile: the eight waves split K instead (see ksplit_last_block)
+        nmfma += ksplit_last_block(CT, (const smem<const long long> *)kaddr, panel, Pb, (smem<double> *)As, M, Kc, kc,
+                                   rb * BM, colact);
+        continue;
+      }
       const int r = rb * BM + (tid & (BM - 1));
       const bool rok = r < M;
       const int rc = rok ? r : 0;  // an in-bounds row for the loads of rows past M
