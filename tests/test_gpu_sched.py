@@ -174,8 +174,8 @@ def test_learned_order_on_uneven_cells(tmp_path):
     med = {k: float(np.median(v[0][1:])) for k, v in res.items()}
     log("median main-kernel ms (builds 2..4): " + ", ".join(f"{k} {v:.1f}" for k, v in med.items()))
     ratio = med["mlp"] / med["exact"]
-    verdict = "gain" if ratio < 0.99 else ("loss" if ratio > 1.01 else "neutral (within 1%)")
-    log(f"learned order vs LPT on exact costs of the previous build: {ratio:.4f} -> {verdict}; "
+    outcome = "gain" if ratio < 0.99 else ("loss" if ratio > 1.01 else "neutral (within 1%)")
+    log(f"learned order vs LPT on exact costs of the previous build: {ratio:.4f} -> {outcome}; "
         f"vs the static |N(A)||N(B)| LPT: {med['mlp'] / med['lpt']:.4f}; vs norm-sorted packing: "
         f"{med['mlp'] / med['norm']:.4f}")
     assert r_mlp > r_static
