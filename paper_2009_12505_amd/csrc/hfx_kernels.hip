@@ -890,6 +890,14 @@ __device__ void phase_masks(const DevPlan &P, ItemLds &L, gmem<double> *slot, co
   if (lane == 0 && nm) atomicAdd(&L.cnt[kCntMfmaY], nm);
 }
 
+// the masks phase out of line, with a register allocation of its own: in the kernels that carry
+// the FP32 tier (and not split-BF16x3) this measured faster; in the others inline is faster
+__device__ __noinline__ void phase_masks_ool(const DevPlan &P, ItemLds &L, gmem<double> *slot, const gmem<int> *dfg,
+                                            const gmem<long long> *doff, gmem<uint8_t> *mask, gmem<double> *E2,
+                                            gmem<double> *wreg, gmem<float> *ub) {
+  phase_masks(P, L, slot, dfg, doff, mask, E2, wreg, ub);
+}
+
 __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
   return (L.f_on[i] ? 0.5 : 1.0) * (L.g_on[j] ? 0.5 : 1.0);
 }
@@ -1831,7 +1839,10 @@ __global__ __launch_bounds__(NT) void k_main(DevPlan P, KParams kp) {
     }
     tick(1);
     gmem<float> *ub = (kp.tier == 1 || kp.tier == 3) ? reinterpret_cast<gmem<float> *>(slot + kp.ub_off) : nullptr;
-    phase_masks(P, L, slot, dfg, doff, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
+    if constexpr (PR == 1)
+      phase_masks_ool(P, L, slot, dfg, doff, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
+    else
+      phase_masks(P, L, slot, dfg, doff, mask, E2, slot + kp.wave_off + (tid >> 6) * kp.wave_doubles, ub);
     // decode tables
     for (int r = tid; r < L.MR; r += NT) {
       int lo = 0, hi = L.nF - 1;
