@@ -16,6 +16,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -89,19 +90,19 @@ def progress(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
-    """sha256 over the sources of the main kernel (its body and the shared device structures)."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in ("hfx_kernels.hip", "hfx_internal.h"):
-        with open(os.path.join(ROOT, "paper_2009_12505_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+def kernel_code_digest(tile_r: int):
+    """Digest of the machine code of the FP64 main kernel with this terms-3/4 output width and of the
+    functions it calls, in the in-tree library (None without the ROCm disassembler)."""
+    from paper_2009_12505_amd import codeid
+    try:
+        return codeid.kernel_code_digest(codeid.k_main_symbol(tile_r, 0))
+    except (KeyError, OSError, subprocess.CalledProcessError):
+        return None
 
 
-def measured_traffic(eps: float):
+def measured_traffic(eps: float, tile_r: int):
     """HBM bytes per launch of the main kernel from the committed counter summary, if it was
-    taken on the current kernel source and this workload (else None)."""
+    taken on this workload and on the same machine code as the kernel timed here (else None)."""
     path = os.path.join(ROOT, "profiles", f"k_main_cfg3_eps{eps:g}_hbm_bytes.txt")
     if not os.path.exists(path):
         return None
@@ -111,7 +112,10 @@ def measured_traffic(eps: float):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256") != kernel_source_digest():
+    if fields.get("tile_r") != str(tile_r):
+        return None
+    code = kernel_code_digest(tile_r)
+    if code is None or fields.get("kernel_code_sha256") != code:
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -415,7 +419,7 @@ def main():
                                        "terms12": st["mfma_flops"][2]},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": round(peak, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(args.eps) if (args.precision == "fp64" and args.workload == "cfg3")
+                     "traffic": measured_traffic(args.eps, st["tile_r"]) if (args.precision == "fp64" and args.workload == "cfg3")
                      else None,
                      "kernel": "hfx::k_main", "kernel_ms": round(ms_k, 3),
                      "flops_per_launch": fl_paper, "flop_count": "Algorithm 3 (same as value)",
