@@ -64,7 +64,7 @@ typedef enum {
   HFX_ERR_OOM = 4,         /* device allocation failed or exceeds max_device_bytes            */
   HFX_ERR_HIP = 5,         /* a HIP runtime call failed (plan is poisoned)                    */
   HFX_ERR_STATE = 6,       /* D does not match the plan's pattern, or poisoned plan           */
-  HFX_ERR_UNSUPPORTED = 7  /* option value not implemented                                    */
+  HFX_ERR_UNSUPPORTED = 7  /* option value not implemented, or a size beyond the limits below */
 } hfx_status;
 
 typedef struct {
@@ -211,6 +211,11 @@ typedef struct hfx_plan hfx_plan;
  *   D_pattern   n_cells D block structures (row/col/R/off; data may be NULL)
  *   th          thresholds; opt: options (NULL = defaults)
  *   out         receives the plan
+ * Limits of this implementation (HFX_ERR_UNSUPPORTED, with the reason in hfx_last_error):
+ * n_ao of a species 1..32 and n_abf 1..512; at most 160 kept C blocks (neighbours F of
+ * Sec. III B 1) per atom; lattice vector indices within +-200; per-item tables that fit the
+ * decode tables and 160 KB of LDS per workgroup.  HFX_ERR_OOM when the device footprint
+ * exceeds max_device_bytes or an allocation fails.
  * Synchronises before returning. */
 hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blocks *C, const hfx_blocks *V,
                            const hfx_blocks *D_pattern, const hfx_thresholds *th, const hfx_options *opt,
