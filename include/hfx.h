@@ -221,8 +221,9 @@ hfx_status hfx_plan_create(int32_t n_cells, const hfx_cell *cells, const hfx_blo
                            const hfx_blocks *D_pattern, const hfx_thresholds *th, const hfx_options *opt,
                            hfx_plan **out);
 
-/* Layout of Sigma for one cell: the D pattern's row/col/R with compact
- * offsets (running sum of n_ao(row)*n_ao(col) in block order).  The arrays
+/* Layout of Sigma for one cell.  Sigma^X_{Ii,Jj}(R) of eq. HFX_ERIs is formed on the
+ * real-space block pattern of D (Sec. III B 3, the sparsity of D): the D pattern's
+ * row/col/R with compact offsets (running sum of n_ao(row)*n_ao(col) in block order).  The arrays
  * are owned by the plan (host memory, valid until hfx_plan_destroy);
  * layout->data is NULL.  *n_elements receives the FP64 count of the cell's
  * Sigma buffer. */
@@ -239,8 +240,9 @@ hfx_status hfx_sigma_layout(const hfx_plan *plan, int32_t cell, hfx_blocks *layo
  * the stream has passed this call's work. */
 hfx_status hfx_build(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, hfx_build_stats *stats);
 
-/* E_x = 1/2 <D, Sigma^X> per cell with compensated FP64 summation over the
- * D pattern; D as in hfx_build, sigma device buffers from hfx_build.
+/* E_x = 1/2 <D, Sigma^X> per cell (the exchange energy of the matrix of eq. HFX_ERIs
+ * with the density matrix of eq. DM_realspace; Sigma^X = -K, no spin factor) with
+ * compensated FP64 summation over the D pattern; D as in hfx_build, sigma device buffers from hfx_build.
  * e_x: n_cells host doubles.  Synchronises. */
 hfx_status hfx_energy(hfx_plan *plan, const hfx_blocks *D, double *const *sigma, double *e_x);
 
