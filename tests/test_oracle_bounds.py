@@ -10,7 +10,10 @@ factors from the other side:
 * the factors themselves against their definitions, evaluated independently through
   singular values (sqrt||X X^T||_F is the Schatten-4 norm (sum sigma^4)^(1/4));
 * per-stage, per-term kept counts against a brute-force numpy enumeration of the
-  three bounds on a tiny periodic cell.
+  three bounds on a tiny periodic cell, and the CS-ERI kept count against an enumeration
+  of Q_AF Q_BG > eps (Sec. III C 2);
+* the max-abs pre-screening of C, V and D (Sec. III B) against its plain definition:
+  the unscreened build of the same tensors with the dropped blocks set to zero.
 """
 import numpy as np
 import pytest
@@ -184,3 +187,61 @@ def test_kept_counts_equal_bruteforce_enumeration(eps):
     got = np.array([[r.stats[f"kept_s{s}_t{t}"] for t in (1, 2, 3, 4)] for s in (1, 2, 3)])
     assert want[0].sum() > want[2].sum() > 0, want
     np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("quantile", [0.2, 0.5, 0.8])
+def test_cs_eri_counts_equal_bruteforce_enumeration(quantile):
+    """With only the CS-ERI test on (eq. CS-ERI, Sec. III C 2), a quartet (A a, F f | B b, G g) is
+    kept iff Q_AF Q_BG > eps: the oracle's visited and kept counts equal a plain enumeration over
+    every <A,B> item, F of A and G of B, with Q_AF taken from the oracle's per-block values (which
+    test_cs_eri_q_is_max_diagonal_eri pins against the explicit four-centre integrals).  The
+    threshold sits at a quantile of the products, so both outcomes occur."""
+    w = _random_workload()
+    cell = w.cells[0]
+    C = w.C[0]
+    r0 = oracle.run(cell, C, w.V[0], w.D[0], {k: 0.0 for k in w.thresholds}, stages=oracle.CS_ERI, norms=True,
+                    n_threads=2)
+    Q = {(int(C.row[k]), int(C.col[k]), tuple(int(x) for x in C.R[k])): r0.norms["Q"][k] for k in range(C.n_blocks)}
+    by_row = {}
+    for (a, f, R), q in Q.items():
+        by_row.setdefault(a, []).append(q)
+    prods = [qf * qg for (A, B, _R) in w.V[0].as_dict(cell) for qf in by_row.get(A, []) for qg in by_row.get(B, [])]
+    eps = float(np.quantile(prods, quantile))
+    th = {k: 0.0 for k in w.thresholds}
+    th["eps_cs_eri"] = eps
+    r = oracle.run(cell, C, w.V[0], w.D[0], th, stages=oracle.CS_ERI, n_threads=2)
+    assert r.stats["candidates"] == len(prods)
+    want = sum(1 for p in prods if p > eps)
+    assert 0 < want < len(prods)
+    assert r.stats["kept_cs_eri"] == want
+
+
+def _zeroed(X, cell, ks):
+    data = X.data.copy()
+    for k in ks:
+        o = int(X.off[k])
+        data[o:o + X.block(cell, k).size] = 0.0
+    return hs.Blocks(X.row, X.col, X.R, X.off, data, X.kind)
+
+
+@pytest.mark.parametrize("which", ["C", "V", "D"])
+def test_prescreen_is_dropping_small_blocks(which):
+    """Pre-screening (Sec. III B: a C, V or D block whose largest element is at most its threshold
+    is discarded) gives exactly the unscreened Sigma of the same tensors with those blocks set to
+    zero.  The threshold of the tensor under test sits at the median of its block maxima; the
+    others are 0 (keep every non-zero block); no Cauchy-Schwarz stage is on."""
+    w = _random_workload()
+    cell = w.cells[0]
+    X = {"C": w.C[0], "V": w.V[0], "D": w.D[0]}
+    mx = np.array([np.abs(X[which].block(cell, k)).max() for k in range(X[which].n_blocks)])
+    eps = float(np.median(mx))
+    small = np.nonzero(mx <= eps)[0]
+    assert 0 < len(small) < len(mx)
+    th = {k: 0.0 for k in w.thresholds}
+    th[f"eps_{which}"] = eps
+    r_pre = oracle.run(cell, w.C[0], w.V[0], w.D[0], th, stages=oracle.PRE, n_threads=2)
+    X[which] = _zeroed(X[which], cell, small)
+    r_zero = oracle.run(cell, X["C"], X["V"], X["D"], {k: 0.0 for k in w.thresholds}, stages=0, n_threads=2)
+    assert np.abs(r_zero.sigma).max() > 0
+    np.testing.assert_allclose(r_pre.sigma, r_zero.sigma, rtol=0, atol=1e-14 * np.abs(r_zero.sigma).max())
+    assert r_pre.stats["units_formed"] < r_zero.stats["units_formed"]
