@@ -16,7 +16,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import subprocess
 import sys
 import time
 
@@ -93,10 +92,10 @@ def progress(msg):
 def kernel_code_digest(tile_r: int):
     """Digest of the machine code of the FP64 main kernel with this terms-3/4 output width and of the
     functions it calls, in the in-tree library (None without the ROCm disassembler)."""
-    from paper_2009_12505_amd import codeid
     try:
+        from paper_2009_12505_amd import codeid
         return codeid.kernel_code_digest(codeid.k_main_symbol(tile_r, 0))
-    except (KeyError, OSError, subprocess.CalledProcessError):
+    except Exception:  # an annotation of the bench line: without it traffic is reported as null
         return None
 
 
