@@ -99,6 +99,19 @@ def kernel_code_digest(tile_r: int):
         return None
 
 
+def measured_peak(kind: str, achieved: float):
+    """The matrix-core peak of this GPU measured by the library's probe (outside the timed region),
+    beside the data-sheet peak the roofline fraction is quoted against; None if the probe fails."""
+    try:
+        from paper_2009_12505_amd import peak
+        tf, mhz = peak.mfma_peak(kind)
+    except Exception as e:  # an annotation of the bench line, never a reason to lose it
+        progress(f"matrix-core probe failed: {e}")
+        return None
+    return {"kind": kind, "tflops": round(tf, 2), "sclk_mhz": round(mhz, 1),
+            "datasheet_tflops": peak.DATASHEET_TFLOPS[kind], "frac_of_measured": round(achieved / tf, 4)}
+
+
 def measured_traffic(eps: float, tile_r: int):
     """HBM bytes per launch of the main kernel from the committed counter summary, if it was
     taken on this workload and on the same machine code as the kernel timed here (else None)."""
@@ -431,6 +444,10 @@ def main():
         "phase_share": st["phase_share"], "plan_s": round(t_plan, 2), "gen_s": round(t_gen, 2),
         "wall_s_timed": round(t_wall, 3),
     }
+    if args.precision == "fp64":
+        pm = measured_peak("fp64", achieved)
+        if pm is not None:
+            out["roofline"]["peak_measured"] = pm
     if args.workload != "cfg3":
         args.fourier_reps = 0
         args.mixed_steps = 0

@@ -358,6 +358,20 @@ hfx_status hfx_item_features(hfx_plan *plan, const float *mu, const float *sd, f
  * written into buf (len bytes, NUL-terminated).  HFX_ERR_ARG if buf is too small. */
 hfx_status hfx_tune_key(const hfx_plan *plan, char *buf, int32_t len);
 
+/* Dense matrix-core throughput of the current GPU, measured: the peak the roofline fraction of
+ * the build (an MFMA-bound dense block contraction, Algorithm 3 and Table multiply) is judged
+ * against, taken on this part rather than from its data sheet.  Every wave of a grid that fills all
+ * compute units issues independent chains of one MFMA instruction on register operands:
+ *   kind 0  FP64  16x16x4  (2048 FLOP per instruction)
+ *   kind 1  FP32  16x16x4  (2048)
+ *   kind 2  BF16  16x16x32 with FP32 sums (16384)
+ * tflops (host) receives FLOPs / kernel time / 1e12, 2 FLOPs per multiply-add; sclk_mhz (host,
+ * optional) the shader clock during the run, from the cycle counter against the constant-rate wall
+ * clock.  About 60 ms of GPU time on stream (NULL = default).  Allocates and frees a small device
+ * buffer; synchronises.  Errors: HFX_ERR_ARG for another kind or NULL tflops, HFX_ERR_OOM,
+ * HFX_ERR_HIP. */
+hfx_status hfx_mfma_peak(int32_t kind, void *stream, double *tflops, double *sclk_mhz);
+
 void hfx_plan_destroy(hfx_plan *plan);
 const char *hfx_last_error(void);
 int32_t hfx_abi_version(void);

@@ -20,7 +20,7 @@ SCHED_PLAN, SCHED_LPT, SCHED_MLP, SCHED_EXACT, SCHED_NORM, SCHED_KMEANS = 0, 1, 
 EXPORTED = ["hfx_plan_create", "hfx_sigma_layout", "hfx_build", "hfx_energy", "hfx_item_profile",
             "hfx_plan_destroy", "hfx_last_error", "hfx_abi_version", "hfx_mlp_n_params", "hfx_mlp_predict",
             "hfx_mlp_loss_grad", "hfx_mlp_train", "hfx_item_features", "hfx_sigma_to_k",
-            "hfx_density_from_k", "hfx_mlp_train_static", "hfx_tune_key"]
+            "hfx_density_from_k", "hfx_mlp_train_static", "hfx_tune_key", "hfx_mfma_peak"]
 ITEM_UNITS = 5
 ITEM_FEATURES = 10
 ITEM_TARGETS = 2
@@ -136,6 +136,8 @@ def lib():
         L.hfx_item_features.argtypes = [P, P, P, P]
         L.hfx_sigma_to_k.restype = ctypes.c_int
         L.hfx_sigma_to_k.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P, P]
+        L.hfx_mfma_peak.restype = ctypes.c_int
+        L.hfx_mfma_peak.argtypes = [ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.hfx_density_from_k.restype = ctypes.c_int
         L.hfx_density_from_k.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P, P]
         if L.hfx_abi_version() != ABI_VERSION:

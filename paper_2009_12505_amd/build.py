@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhfx.so")
-SOURCES = ["hfx_plan.hip", "hfx_kernels.hip", "hfx_mlp.hip", "hfx_fourier.hip"]
+SOURCES = ["hfx_plan.hip", "hfx_kernels.hip", "hfx_mlp.hip", "hfx_fourier.hip", "hfx_peak.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -65,6 +65,10 @@ int mlp_scratch_max_params();
 int mlp_max_h();
 int mlp_max_f();
 int mlp_max_o();
+hipError_t mfma_peak_run(int kind, int n_cu, int iters, double *out, long long *clk, hipStream_t st, float *ms,
+                         double *flops);
+int mfma_peak_blocks_per_cu();
+int mfma_peak_threads();
 }  // namespace hfx
 
 using namespace hfx;
@@ -1482,6 +1486,41 @@ hfx_status hfx_mlp_train_static(int32_t n_in, int32_t n_hidden, int32_t n_out, f
     (void)hipGetLastError();
     return fail(HFX_ERR_HIP, "training launch failed: %s", hipGetErrorString(e));
   }
+  return HFX_OK;
+}
+
+hfx_status hfx_mfma_peak(int32_t kind, void *stream, double *tflops, double *sclk_mhz) {
+  if (kind < 0 || kind > 2 || !tflops) return fail(HFX_ERR_ARG, "kind must be 0, 1 or 2 and tflops non-NULL");
+  int dev = 0, wall_khz = 0;
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
+  if (e != hipSuccess) return fail(HFX_ERR_HIP, "device query: %s", hipGetErrorString(e));
+  const int n_cu = prop.multiProcessorCount;
+  const int iters = kind == 0 ? 32768 : kind == 1 ? 65536 : 131072;  // about 50 ms each at 2.4 GHz
+  double *out = nullptr;
+  long long *clk = nullptr;
+  const size_t n_out = (size_t)n_cu * mfma_peak_blocks_per_cu() * mfma_peak_threads();
+  if (hipMalloc((void **)&out, n_out * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&clk, 2 * sizeof(long long)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(out);
+    return fail(HFX_ERR_OOM, "probe buffers");
+  }
+  float ms = 0.f;
+  double flops = 0.0;
+  long long hclk[2] = {0, 0};
+  e = mfma_peak_run(kind, n_cu, iters, out, clk, (hipStream_t)stream, &ms, &flops);
+  if (e == hipSuccess) e = hipMemcpy(hclk, clk, sizeof(hclk), hipMemcpyDeviceToHost);
+  (void)hipFree(out);
+  (void)hipFree(clk);
+  if (e != hipSuccess) return fail(HFX_ERR_HIP, "matrix-core probe: %s", hipGetErrorString(e));
+  if (!(ms > 0.f)) return fail(HFX_ERR_HIP, "matrix-core probe: no elapsed time");
+  *tflops = flops / ((double)ms * 1e-3) / 1e12;
+  if (sclk_mhz)
+    *sclk_mhz = (wall_khz > 0 && hclk[1] > 0) ? (double)hclk[0] / ((double)hclk[1] / ((double)wall_khz * 1e3)) / 1e6
+                                               : 0.0;
   return HFX_OK;
 }
 

@@ -226,3 +226,11 @@ def test_library_shares_torchs_hip_runtime():
             "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
     out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT, text=True).strip().splitlines()[-1]
     assert out == "1", out
+
+
+def test_mfma_peak_rejects_bad_arguments_before_any_launch():
+    tf = ctypes.c_double(0.0)
+    assert A.lib().hfx_mfma_peak(3, None, ctypes.byref(tf), None) == A.HFX_ERR_ARG
+    assert A.lib().hfx_mfma_peak(-1, None, ctypes.byref(tf), None) == A.HFX_ERR_ARG
+    assert A.lib().hfx_mfma_peak(0, None, None, None) == A.HFX_ERR_ARG
+    assert "kind" in A.lib().hfx_last_error().decode()
