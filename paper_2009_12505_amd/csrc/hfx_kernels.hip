@@ -18,9 +18,14 @@
 //            units), contracted with Y_G in the epilogue: term 1 summed over F and
 //            G into Sigma(A,B), term 2 summed over F into Sigma(A,G)
 //
-// Contractions use the FP64 matrix cores (v_mfma_f64_16x16x4f64), one 16x16
-// output tile per wave at a time; a tile whose (F,G) blocks are all screened
-// out is skipped.  Sigma accumulation is FP64 (global atomics).
+// Contractions are block products on the matrix cores: a 128-row output block
+// (tile_r = 32, 64 or 128 columns for terms 3/4, 64 for terms 1/2) per step of the
+// workgroup, its 16x16 tiles shared by the eight waves, K staged through LDS in
+// chunks with a two-chunk register prefetch.  FP64 (v_mfma_f64_16x16x4f64) by
+// default; in the tiered forms a block whose kept units all have small stage-2
+// bounds runs on FP32 (v_mfma_f32_16x16x4f32) or as split-BF16x3 (three
+// v_mfma_f32_16x16x32_bf16 per product).  A tile whose (F,G) blocks are all
+// screened out is skipped.  Sigma accumulation is FP64 (global atomics).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
