@@ -908,7 +908,7 @@ __device__ __forceinline__ double unit_weight(const ItemLds &L, int i, int j) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Workgroup block products: a 128-row x W-column output block (W = 64 or 32), K streamed through
+// Workgroup block products: a 128-row x W-column output block (W = 128, 64 or 32), K streamed through
 // two LDS stages in chunks.  Every thread fetches its share of a chunk's A and B elements into
 // registers two chunks ahead: the loads of chunk c+2 are issued before the MFMAs of chunk c, and
 // chunk c+1 (fetched one chunk earlier) is stored into the other stage after them, so a load has
