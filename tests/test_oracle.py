@@ -166,12 +166,18 @@ def test_home_atom_additivity():
 def test_supercell_equals_primitive_with_images(eps):
     """Unit cell with images == Gamma-only supercell (Sec. IV A, k mesh vs supercell):
     with translation-keyed blocks, every block of the 8-atom conventional cell equals
-    the block of the 2-atom primitive cell between the same two atom positions."""
+    the block of the 2-atom primitive cell between the same two atom positions, and every
+    count of the screening (candidates, kept per stage and term, Y and units formed) is
+    the primitive cell's per atom (the linear scaling of Sec. III B)."""
     kw = dict(species_table=((2, 3),), r_c=6.0, r_v=6.0, r_d=7.0, seed=77, eps=eps)
     wp = hs.make_workload("tiny", kind="primitive", **kw)
     ws = hs.make_workload("tiny", kind="conventional", **kw)
-    sp = oracle.sigma_dict(wp.cells[0], wp.D[0], _run(wp).sigma)
-    ss = oracle.sigma_dict(ws.cells[0], ws.D[0], _run(ws).sigma)
+    rp, rs = _run(wp), _run(ws)
+    sp = oracle.sigma_dict(wp.cells[0], wp.D[0], rp.sigma)
+    ss = oracle.sigma_dict(ws.cells[0], ws.D[0], rs.sigma)
+    # linear scaling: every home atom of the crystal keeps the same work at every stage
+    for k in oracle.STAT_NAMES:
+        assert rs.stats[k] * wp.cells[0].n_atoms == rp.stats[k] * ws.cells[0].n_atoms, k
     pi, pR = hs.map_to_primitive(ws.cells[0], wp.cells[0])
     Lsup, Lp_inv = ws.cells[0].lattice, np.linalg.inv(wp.cells[0].lattice)
     m = 0.0
