@@ -236,3 +236,31 @@ def test_stage_counts_are_nested():
         assert st[f"kept_s1_t{t}"] >= st[f"kept_s2_t{t}"] >= st[f"kept_s3_t{t}"]
     assert st["units_formed"] == sum(st[f"kept_s3_t{t}"] for t in (1, 2, 3, 4))
     assert st["candidates"] >= st["kept_cs_eri"]
+
+
+def _random_shape(seed):
+    """A seeded tiny cell of random shape: one or two species with n_ao in 1..3 and n_abf in 1..5
+    (fewer ABFs than AOs allowed), random ranges for C, V and D."""
+    rng = np.random.default_rng(seed)
+    n_sp = int(rng.integers(1, 3))
+    table = tuple((int(rng.integers(1, 4)), int(rng.integers(1, 6))) for _ in range(n_sp))
+    r_c = float(rng.uniform(4.5, 7.5))
+    cfg = dict(kind="primitive", species_table=table, r_c=r_c, r_v=float(rng.uniform(4.0, 8.0)),
+               r_d=float(rng.uniform(r_c, r_c + 2.5)), seed=1000 + seed)
+    if n_sp == 2:
+        cfg["species"] = [0, 1]
+    return cfg
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_oracle_equals_bruteforce_random_shapes(seed):
+    """As test_oracle_equals_bruteforce, on seeded random block shapes and ranges (Algorithm 1 against
+    Algorithms 2/3 at eps = 0)."""
+    w = hs.make_workload("tiny", **_random_shape(seed))
+    cell = w.cells[0]
+    ref = bf.sigma(cell, w.C[0], w.V[0], w.D[0])
+    r = _run(w)
+    got = oracle.sigma_dict(cell, w.D[0], r.sigma)
+    scale = max(float(np.abs(v).max()) for v in ref.values())
+    assert scale > 0
+    assert _maxdiff(got, ref) <= 1e-12 * scale
