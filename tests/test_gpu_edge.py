@@ -1,6 +1,6 @@
 """Degenerate and extreme inputs on the GPU against the oracle: everything screened out, no
-home atoms, a single isolated atom (one work item, on-site units only), and the largest block
-the kernels take (32 AOs per atom)."""
+home atoms, a single isolated atom (one work item, on-site units only), the largest block the
+kernels take (32 AOs per atom) and the smallest (one AO or one ABF per atom)."""
 import numpy as np
 import pytest
 
@@ -51,6 +51,21 @@ def test_largest_block_size():
     ref = _ref(w)
     sig, e, st = gpu_build(w)
     check_close(sig[0], ref.sigma, label="n_ao 32")
+    for t in (1, 2, 3, 4):
+        assert st[f"kept_s3_t{t}"] == ref.stats[f"kept_s3_t{t}"]
+
+
+@pytest.mark.parametrize("table", [((1, 1), (1, 3)), ((3, 1), (2, 1)), ((1, 2), (3, 5))])
+def test_smallest_block_sizes(table):
+    """One AO or one ABF per atom (blocks from 1x1 up): the degenerate end of the block shapes, next
+    to slightly larger ones, in a two-species conventional cell."""
+    log(f"case smallest blocks {table}")
+    w = hs.make_workload("tiny", kind="conventional", species_table=table, species=[0, 1] * 4, r_c=6.0, r_v=7.0,
+                         r_d=8.0, eps=1e-6)
+    ref = _ref(w)
+    sig, e, st = gpu_build(w)
+    check_close(sig[0], ref.sigma, label=f"blocks {table}")
+    assert abs(e[0] - oracle.energy(w.cells[0], w.D[0], ref.sigma)) <= 1e-11 * abs(e[0]) + 1e-300
     for t in (1, 2, 3, 4):
         assert st[f"kept_s3_t{t}"] == ref.stats[f"kept_s3_t{t}"]
 
