@@ -224,3 +224,19 @@ def test_cfg4_batched_cells_home_subset():
         ref = oracle.run(cell, w.C[k], w.V[k], w.D[k], w.thresholds, home=[home_local[k]], n_threads=16)
         log(f"cfg4 cell {k}: oracle {time.time() - t:.1f}s")
         check_close(sig[k], ref.sigma, label=f"cfg4 cell {k} ({cell.n_atoms} atoms)")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_shapes_parity(seed):
+    """Seeded random block shapes (one or two species, 1..3 AOs and 1..5 ABFs per atom, random C, V
+    and D ranges; the cells the oracle is pinned on against brute force), at eps 0 and 1e-4."""
+    from test_oracle import _random_shape
+    cfg = dict(_random_shape(seed), eps=(0.0, 1e-4)[seed % 2])
+    log(f"case random shape {seed}: {cfg}")
+    w = hs.make_workload("tiny", **cfg)
+    ref = oracle.run(w.cells[0], w.C[0], w.V[0], w.D[0], w.thresholds, n_threads=8)
+    sig, e, st = gpu_build(w)
+    check_close(sig[0], ref.sigma, label=f"random shape {seed}")
+    for t in (1, 2, 3, 4):
+        assert st[f"kept_s3_t{t}"] == ref.stats[f"kept_s3_t{t}"]
+    assert st["g_alive"] == ref.stats["y_formed"]
