@@ -66,3 +66,10 @@ def test_supercell_blocks_equal_primitive_blocks():
             q = prim[(int(pi[i]), int(pi[j]), Rp)]
             m = n[pi[i]] * n[pi[j]]
             assert np.array_equal(Bs.data[Bs.off[b]:Bs.off[b] + m], Bp.data[Bp.off[q]:Bp.off[q] + m])
+
+
+def test_keyed_stream_is_splitmix64():
+    """The counter-based stream behind every keyed block is SplitMix64 (Steele, Lea & Flood 2014):
+    key 0 at counters 0..3 gives the first four outputs of the published generator seeded with 0."""
+    b = hs._bits(np.array([0], np.uint64), np.arange(4, dtype=np.uint64))[0]
+    assert [int(x) for x in b] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
